@@ -1,0 +1,171 @@
+"""Benchmark: one DGR fwd+bwd optimisation iteration on one MI355X.
+
+Workload: 256^3 volume, 100,000 anisotropic Gaussians (scales log-uniform in
+[0.004, 0.03]), cone beam 360 views over 360 degrees onto 512 x 512 pixels at
+0.8 mm, DSO 1000 mm, DSD 1500 mm, march step 0.5 voxel, L1 projection loss
+against the noisy analytic projections of a seeded ellipsoid phantom.  A step
+is voxelize -> project + L1 -> backproject -> voxelize backward -> Adam, with
+all inputs resident in HBM.
+
+Prints ONE JSON line (see the repository's benchmark contract).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+METRIC = "fwd+bwd ms/iter @256^3,100k Gaussians,360 views; s to 35 dB PSNR vs plain"
+
+# MI355X published peaks
+HBM_PEAK_GBS = 8000.0
+FP32_VALU_PEAK_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz, no packed FP32
+
+# Algorithmic work per unit (measurement section)
+FLOP_PER_SAMPLE = {"project_l1": 31.0, "backproject": 34.0}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def count_samples(prob) -> int:
+    """Exact number of ray samples of the geometry (same k-range rule as the
+    projector: every sample with -1 <= u <= D on all axes), in binary64."""
+    from paper_2411_04844_amd import inputs
+    g, geom = prob.grid, prob.geom
+    dev = prob.target.device
+    total = 0
+    for j0 in range(0, geom.n_views, 8):
+        idx = np.arange(j0, min(j0 + 8, geom.n_views))
+        o, d = inputs._ray_dirs(geom, idx, dev, torch)
+        c = o - (o * d).sum(-1, keepdim=True) * d
+        lo = torch.tensor(g.lo, dtype=torch.float64, device=dev)
+        ih = torch.tensor(g.inv_h, dtype=torch.float64, device=dev)
+        dims = torch.tensor(g.dims, dtype=torch.float64, device=dev)
+        cu = (c - lo) * ih - 0.5
+        du = d * ih * geom.step
+        with torch.no_grad():
+            t0 = (-1.0 - cu) / du
+            t1 = (dims - cu) / du
+            tmin = torch.minimum(t0, t1).amax(-1)
+            tmax = torch.maximum(t0, t1).amin(-1)
+            k0, k1 = torch.ceil(tmin), torch.floor(tmax)
+            total += int(torch.clamp(k1 - k0 + 1, min=0).sum().item())
+    return total
+
+
+def cpu_baseline(prob, n_views_sample: int):
+    """Time the binary64 oracle on a bounded sample of the same workload."""
+    import oracle
+    from paper_2411_04844_amd import inputs
+    g = prob.grid
+    P = {k: v.cpu().numpy() for k, v in prob.params.items()}
+    nthreads = oracle.num_threads()
+    t = time.perf_counter()
+    box = oracle.bbox(P["mu"], P["scale"], P["quat"], g.dims, g.lo, g.inv_h)
+    V = oracle.voxelize(P["mu"], P["scale"], P["quat"], P["density"], g.dims, g.lo, g.inv_h, box)
+    t_vox = time.perf_counter() - t
+    sel = np.linspace(0, prob.geom.n_views - 1, n_views_sample).round().astype(int)
+    views = prob.geom.views[sel]
+    y = prob.target[sel].cpu().numpy()
+    t = time.perf_counter()
+    Ph = oracle.project(V, g.dims, g.lo, g.inv_h, prob.geom.kind, views, prob.geom.nu, prob.geom.nv,
+                        prob.geom.step, prob.geom.length_scale)
+    _, gr = oracle.l1(Ph, y)
+    t_proj = time.perf_counter() - t
+    t = time.perf_counter()
+    dV = oracle.backproject(gr, g.dims, g.lo, g.inv_h, prob.geom.kind, views, prob.geom.nu,
+                            prob.geom.nv, prob.geom.step, prob.geom.length_scale)
+    t_bp = time.perf_counter() - t
+    t = time.perf_counter()
+    oracle.voxelize_grad(P["mu"], P["scale"], P["quat"], P["density"], g.dims, g.lo, g.inv_h, box, dV)
+    t_grad = time.perf_counter() - t
+    scale = prob.geom.n_views / n_views_sample
+    ms = 1e3 * (t_vox + t_grad + (t_proj + t_bp) * scale)
+    wall = t_vox + t_proj + t_bp + t_grad
+    return {"value": round(ms, 1), "unit": "ms/iter", "cores": nthreads, "kind": "oracle",
+            "sample": (f"binary64 oracle: full voxelization and voxelization gradient "
+                       f"(100k Gaussians, 256^3), projection+L1 and backprojection over "
+                       f"{n_views_sample} of 360 views scaled x{scale:.1f}; {wall:.1f} s wall")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-views", type=int, default=24, help="views in the oracle's timed sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2411_04844_amd import native, recon
+    native.lib()  # fail loudly if the HIP library is missing
+    torch.cuda.init()
+    log("building workload (256^3, 100k Gaussians, 360 x 512^2 cone)")
+    prob = recon.cone_problem(device="cuda")
+    it = recon.Iteration(prob)
+    samples = count_samples(prob)
+    log(f"pairs capacity {it.max_pairs}, ray samples per projection {samples:.4g}")
+
+    for _ in range(args.warmup):
+        it.step()
+    torch.cuda.synchronize()
+    it.check()
+
+    events = {}
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record()
+    for i in range(args.steps):
+        it.step(events=events)
+        log(f"step {i + 1}/{args.steps} enqueued")
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    it.check()
+    ms = start.elapsed_time(stop) / args.steps
+    stage_ms = {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in events.items()}
+    log("stage ms:", json.dumps({k: round(v, 3) for k, v in stage_ms.items()}),
+        f"wall {wall:.2f}s loss {float(it.loss):.6g}")
+
+    dom = max(FLOP_PER_SAMPLE, key=lambda k: stage_ms[k])
+    achieved = FLOP_PER_SAMPLE[dom] * samples / (stage_ms[dom] * 1e-3) / 1e12
+    roofline = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 3),
+                "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP32_VALU_PEAK_TFLOPS, 4), "traffic": None}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a sample of the workload")
+        cpu = cpu_baseline(prob, args.cpu_views)
+
+    out = {
+        "metric": METRIC, "value": round(ms, 3), "unit": "ms/iter", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "dgr_cone_fwd_bwd_256^3_100k_gauss_360x512^2",
+                   "volume": 256, "gaussians": 100000, "views": 360, "detector": 512,
+                   "ray_samples": samples, "pair_capacity": it.max_pairs},
+        "stage_ms": {k: round(v, 3) for k, v in stage_ms.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * dgr.h -- C ABI of libdgr.so, the MI355X (gfx950) hot path of Discretized
+ * Gaussian Representation (DGR) CT reconstruction (Wu et al., arXiv
+ * 2411.04844).
+ *
+ * The library turns a set of 3-D Gaussians into a voxel volume (sec. 4.1-4.2,
+ * Fast Volume Reconstruction, Alg. 1), projects the volume along X-ray paths
+ * (sec. 4.3, P_hat = T(V); sec. 3, y = Ax), and provides the exact adjoints of
+ * both, so that a projection-domain loss can be differentiated with respect to
+ * every Gaussian parameter.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Memory: every array argument is a DEVICE pointer (HIP), contiguous and
+ *   row-major, binary32 unless stated.  The caller allocates and owns every
+ *   buffer, including the workspace `ws`; the library keeps no device state
+ *   between calls and never allocates device memory.
+ * - Streams: `stream` is a hipStream_t (NULL = the default stream).  Every call
+ *   only enqueues work and returns; the only call that waits for the device is
+ *   dgr_voxelize_plan (it returns a count to the host) and dgr_check.
+ * - Outputs are overwritten, never accumulated into.
+ * - Errors: argument checks happen on the host before anything is enqueued;
+ *   on failure nothing is launched and a status other than DGR_OK is
+ *   returned.  dgr_last_error() gives a thread-local description.  No call
+ *   aborts or throws.  A pair-capacity overflow found on the device is
+ *   recorded in the workspace; the affected volume is filled with NaN and
+ *   dgr_check() (or the next dgr_voxelize_plan) reports DGR_ERR_CAPACITY.
+ * - Calls that share a workspace must not overlap; distinct workspaces may
+ *   be used concurrently on different streams.
+ *
+ * Coordinates
+ * -----------
+ * World points are (x, y, z).  A grid of dims (nx, ny, nz) has its lower faces
+ * at lo[] and voxel size 1/inv_h[a] on axis a; voxel (i, j, k) has its centre
+ * at lo + (idx + 1/2)/inv_h and is stored at [k][j][i] (x fastest).  The
+ * continuous voxel coordinate of a point p is u = (p - lo)*inv_h - 1/2, so
+ * voxel centres sit at integers (the integer grid of the paper's Discretize
+ * and Align step, sec. 4.1).
+ */
+#ifndef DGR_H
+#define DGR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DGR_OK = 0,
+    DGR_ERR_INVALID_ARG = 1, /* null pointer, bad size or unsupported shape       */
+    DGR_ERR_WORKSPACE = 2,   /* workspace too small or not 256-byte aligned        */
+    DGR_ERR_CAPACITY = 3,    /* more (tile, Gaussian) pairs than the workspace holds */
+    DGR_ERR_HIP = 4          /* a HIP runtime call failed; see dgr_last_error()    */
+} dgr_status;
+
+/* Voxel grid.  dims[a] in [1, 16384]; inv_h[a] > 0. */
+typedef struct {
+    int32_t dims[3];
+    float lo[3];
+    float inv_h[3];
+} dgr_grid;
+
+/* Truncation of each Gaussian to an axis-aligned box of voxel centres
+ * (sec. 4.1, Gaussian Effect Confinement; Alg. 1 validity mask).
+ * k_sigma > 0: per-Gaussian box |i_a - u_a| <= k_sigma*sqrt(Sigma_aa)*inv_h_a.
+ * k_sigma <= 0: the paper's fixed cuboid floor(u) +- box_half on every axis.
+ * The box is clamped to the grid.  Its integer bounds are defined by one
+ * binary32 sequence (every operation correctly rounded, no fused
+ * multiply-add, in this order):
+ *   n2 = ((w*w + x*x) + y*y) + z*z;  m = sqrt(n2);  q_hat = q/m  (n2 = 0: R = I)
+ *   R = rotation of q_hat (row a = image components), a_j = R[a][j]*s_j,
+ *   S_aa = (a_0*a_0 + a_1*a_1) + a_2*a_2,  r = (k_sigma*sqrt(S_aa))*inv_h_a,
+ *   u = (mu_a - lo_a)*inv_h_a - 0.5,  lo = ceil(u - r),  hi = floor(u + r),
+ *   then lo clamped to [0, dims], hi to [-1, dims-1]; empty iff lo > hi.    */
+typedef struct {
+    float k_sigma;
+    int32_t box_half;
+} dgr_trunc;
+
+#define DGR_PARALLEL 0
+#define DGR_CONE 1
+
+/* Acquisition geometry.  The paper leaves the projection T abstract
+ * (sec. 4.3); the operator here is the trilinear ray march
+ *   P_hat[r] = length_scale * step * sum_{k in Z} Vbar(c_r + k*step*d_r),
+ * with d_r the unit ray direction, c_r the point of the ray nearest the world
+ * origin and Vbar the trilinear interpolant of the volume on voxel centres,
+ * zero outside the grid.
+ * views: DEVICE pointer, binary32 [n_views][12] =
+ *   { a[3], det[3], e_u[3], e_v[3] }  (world units)
+ * a is the ray direction (DGR_PARALLEL) or the source position (DGR_CONE);
+ * detector pixel (iu, iv) is centred at det + (iu-(nu-1)/2)*e_u +
+ * (iv-(nv-1)/2)*e_v.  Projections are stored [n_views][nv][nu].            */
+typedef struct {
+    int32_t kind;
+    int32_t n_views, nu, nv;
+    const float *views;
+    float step;         /* march step, world units, > 0        */
+    float length_scale; /* multiplies every line integral      */
+} dgr_geometry;
+
+/* ---- voxelization (sec. 4.2 Fast Volume Reconstruction, Alg. 1) -------- */
+
+/* Bytes of workspace that dgr_voxelize / dgr_voxelize_plan / dgr_bin need for
+ * n Gaussians and up to max_pairs (8^3 tile, Gaussian) pairs.  0 on bad
+ * arguments. */
+size_t dgr_voxelize_workspace(int64_t n, int64_t max_pairs, const dgr_grid *grid);
+
+/* Counts the (tile, Gaussian) pairs of the truncation boxes and returns the
+ * count in *n_pairs_host.  Synchronises `stream`.  Also reports an overflow
+ * left in `ws` by an earlier dgr_voxelize (DGR_ERR_CAPACITY, after writing
+ * the new count).  ws must hold dgr_voxelize_workspace(n, 0, grid) bytes. */
+dgr_status dgr_voxelize_plan(const float *mu, const float *scale, const float *quat, int64_t n,
+                             const dgr_grid *grid, const dgr_trunc *trunc, int64_t *n_pairs_host,
+                             void *ws, size_t ws_bytes, void *stream);
+
+/* V(p) = sum_g density_g * exp(-1/2 (p-mu_g)^T Sigma_g^-1 (p-mu_g)) over the
+ * voxel centres p inside each Gaussian's box (sec. 4.1 eq. for V(p); Alg. 1).
+ * mu [n][3], scale [n][3] (> 0, world units), quat [n][4] (w, x, y, z, any
+ * norm; zero = identity), density [n]; Sigma = R diag(scale^2) R^T.
+ * volume [nz][ny][nx] is overwritten.  Contributions to each voxel are added
+ * in ascending Gaussian index, so results are run-to-run deterministic.
+ * The pair capacity is whatever ws holds beyond dgr_voxelize_workspace(n,0). */
+dgr_status dgr_voxelize(const float *mu, const float *scale, const float *quat,
+                        const float *density, int64_t n, const dgr_grid *grid,
+                        const dgr_trunc *trunc, float *volume, void *ws, size_t ws_bytes,
+                        void *stream);
+
+/* Gradient of a scalar loss with respect to the Gaussian parameters, given
+ * dL/dV (dvolume, [nz][ny][nx]); boxes are held fixed (the box edges are not
+ * differentiated).  Outputs dmu [n][3], dscale [n][3], dquat [n][4],
+ * ddensity [n] are overwritten.  ws >= dgr_voxelize_backward_workspace(n). */
+size_t dgr_voxelize_backward_workspace(int64_t n);
+dgr_status dgr_voxelize_backward(const float *mu, const float *scale, const float *quat,
+                                 const float *density, int64_t n, const dgr_grid *grid,
+                                 const dgr_trunc *trunc, const float *dvolume, float *dmu,
+                                 float *dscale, float *dquat, float *ddensity, void *ws,
+                                 size_t ws_bytes, void *stream);
+
+/* ---- projection (sec. 4.3, P_hat = T(V)) and its adjoint --------------- */
+
+/* Bytes of workspace that dgr_project / dgr_project_l1 / dgr_backproject need. */
+size_t dgr_project_workspace(const dgr_grid *grid, const dgr_geometry *geom);
+
+/* proj [n_views][nv][nu] = T(volume). */
+dgr_status dgr_project(const float *volume, const dgr_grid *grid, const dgr_geometry *geom,
+                       float *proj, void *ws, size_t ws_bytes, void *stream);
+
+/* Fused projection and L1 data term (sec. 4.3 objective, L1 part):
+ * *loss (device scalar) = mean_r |P_hat_r - target_r| and
+ * dproj_r = sign(P_hat_r - target_r)/M, sign(0) = 0, M = n_views*nu*nv.
+ * P_hat itself is not stored.  The loss is summed in a fixed order. */
+dgr_status dgr_project_l1(const float *volume, const dgr_grid *grid, const dgr_geometry *geom,
+                          const float *target, float *loss, float *dproj, void *ws,
+                          size_t ws_bytes, void *stream);
+
+/* volume [nz][ny][nx] = T^T(proj): the exact transpose of dgr_project. */
+dgr_status dgr_backproject(const float *proj, const dgr_grid *grid, const dgr_geometry *geom,
+                           float *volume, void *ws, size_t ws_bytes, void *stream);
+
+/* ---- optimiser (sec. 5.1 Implementation Details: Adam) ------------------ */
+
+/* One Adam step in place over n entries:
+ * m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ * param -= lr * (m/(1-b1^step)) / (sqrt(v/(1-b2^step)) + eps);  step >= 1. */
+dgr_status dgr_adam(float *param, const float *grad, float *m, float *v, int64_t n, float lr,
+                    float b1, float b2, float eps, int64_t step, void *stream);
+
+/* ---- inspection ---------------------------------------------------------- */
+
+/* Truncation boxes int32 [n][6] = (lo_x, lo_y, lo_z, hi_x, hi_y, hi_z). */
+dgr_status dgr_bbox(const float *mu, const float *scale, const float *quat, int64_t n,
+                    const dgr_grid *grid, const dgr_trunc *trunc, int32_t *box, void *stream);
+
+/* The sorted (tile, Gaussian) pair list used by dgr_voxelize:
+ * pairs uint32 [P][2] = (tile, gid) ascending, tile = (tz*Ty + ty)*Tx + tx
+ * with T_a = ceil(dims_a/8); tile_begin uint32 [Tx*Ty*Tz + 1].  Needs
+ * P <= capacity of ws; P comes from dgr_voxelize_plan. */
+dgr_status dgr_bin(const float *mu, const float *scale, const float *quat, int64_t n,
+                   const dgr_grid *grid, const dgr_trunc *trunc, uint32_t *pairs,
+                   uint32_t *tile_begin, void *ws, size_t ws_bytes, void *stream);
+
+/* Synchronises `stream` and reports a capacity overflow recorded in a
+ * voxelization workspace (DGR_ERR_CAPACITY) or DGR_OK.  Clears the flag. */
+dgr_status dgr_check(void *ws, void *stream);
+
+const char *dgr_status_string(dgr_status status);
+const char *dgr_last_error(void);
+
+/* Library version, for the binding's load check. */
+int32_t dgr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DGR_H */

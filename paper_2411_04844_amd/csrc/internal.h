@@ -1,0 +1,135 @@
+// Internal declarations shared by the libdgr.so translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+
+#include "dgr.h"
+
+namespace dgr {
+
+// ---- error plumbing --------------------------------------------------------
+dgr_status fail(dgr_status s, const char *fmt, ...);
+
+#define DGR_TRY_HIP(expr)                                                              \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return ::dgr::fail(DGR_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define DGR_CHECK(cond, ...)                                         \
+    do {                                                             \
+        if (!(cond)) return ::dgr::fail(DGR_ERR_INVALID_ARG, __VA_ARGS__); \
+    } while (0)
+
+// Kernel launches report launch failures through hipGetLastError().
+#define DGR_LAUNCH_CHECK() DGR_TRY_HIP(hipGetLastError())
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+dgr_status check_grid(const dgr_grid *g);
+dgr_status check_trunc(const dgr_trunc *t);
+dgr_status check_geometry(const dgr_geometry *g);
+
+// ---- workspace carving -----------------------------------------------------
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Carver {
+    char *base;
+    size_t off = 0;
+    explicit Carver(void *p) : base(static_cast<char *>(p)) {}
+    template <class T>
+    T *take(size_t count) {
+        T *p = reinterpret_cast<T *>(base ? base + off : nullptr);
+        off += align_up(count * sizeof(T));
+        return p;
+    }
+};
+
+// ---- per-Gaussian record written by the prep kernel ------------------------
+// Continuous voxel position u = ui + uf with ui = floor(u) (the paper's
+// floored index) and uf in [0, 1) (its residual Delta mu), the exponent
+// coefficients of exp2, and the packed truncation box.  64 bytes.
+struct alignas(16) GaussRec {
+    int32_t ui[3];
+    float rho;
+    float uf[3];
+    float k00;      // exponent = k00 dx^2 + k11 dy^2 + k22 dz^2
+    float k11, k22; //          + k01 dx dy + k02 dx dz + k12 dy dz  (log2 units)
+    float k01, k02;
+    float k12;
+    uint32_t box[3];  // (lo & 0xffff) | (hi << 16), hi = -1 stored as 0xffff
+};
+static_assert(sizeof(GaussRec) == 64, "record must be 64 bytes");
+
+__host__ __device__ inline int box_lo(uint32_t b) { return (int)(int16_t)(b & 0xffffu); }
+__host__ __device__ inline int box_hi(uint32_t b) { return (int)(int16_t)(b >> 16); }
+
+struct DevGrid {
+    int nx, ny, nz;
+    float lo[3];
+    float inv_h[3];
+};
+inline DevGrid dev_grid(const dgr_grid *g) {
+    DevGrid d;
+    d.nx = g->dims[0];
+    d.ny = g->dims[1];
+    d.nz = g->dims[2];
+    for (int a = 0; a < 3; ++a) {
+        d.lo[a] = g->lo[a];
+        d.inv_h[a] = g->inv_h[a];
+    }
+    return d;
+}
+
+// Enqueue the prep kernel: records + tile counts (and optional int32 boxes).
+dgr_status launch_prep(const float *mu, const float *scale, const float *quat,
+                       const float *density, int64_t n, const dgr_grid *grid,
+                       const dgr_trunc *trunc, GaussRec *rec, uint32_t *tile_count,
+                       int32_t *box_out, hipStream_t st);
+
+// ---- voxelization workspace -----------------------------------------------
+struct VoxHeader {
+    uint32_t overflow;   // set by the emit kernel when pairs > capacity
+    uint32_t pad0;
+    uint64_t total;      // pair count of the last binning
+};
+
+struct VoxWs {
+    VoxHeader *hdr;
+    GaussRec *rec;
+    uint32_t *count;     // tiles per Gaussian
+    uint64_t *offset;    // exclusive scan of count
+    uint64_t *scan_blk;  // block partials of the scan
+    uint32_t *key[2];
+    uint32_t *val[2];
+    uint32_t *hist;      // radix histograms [256][nblk]
+    uint32_t *tile_begin;
+    int64_t cap;
+    int64_t n;
+    int64_t tiles;
+    int radix_blocks;
+    size_t bytes;
+};
+
+VoxWs carve_vox_ws(void *ws, int64_t n, int64_t cap, const dgr_grid *grid);
+int64_t vox_ws_capacity(size_t ws_bytes, int64_t n, const dgr_grid *grid);
+
+// Binning: prep -> count scan -> emit -> stable radix sort -> tile ranges.
+// On return (enqueued) key/val[*which] hold the sorted pairs.
+dgr_status enqueue_binning(const float *mu, const float *scale, const float *quat,
+                           const float *density, int64_t n, const dgr_grid *grid,
+                           const dgr_trunc *trunc, VoxWs &w, int *which, hipStream_t st);
+dgr_status enqueue_count_only(const float *mu, const float *scale, const float *quat, int64_t n,
+                              const dgr_grid *grid, const dgr_trunc *trunc, VoxWs &w,
+                              hipStream_t st);
+
+inline int64_t tiles_of(const dgr_grid *g) {
+    return (int64_t)((g->dims[0] + 7) / 8) * ((g->dims[1] + 7) / 8) * ((g->dims[2] + 7) / 8);
+}
+
+}  // namespace dgr

@@ -1,0 +1,288 @@
+"""ctypes binding of libdgr.so (argument marshalling only).
+
+Every function here has the name of the C entry point it calls and takes
+torch tensors on the GPU; all computation happens in the HIP kernels.  The
+library must have been built (``python -m paper_2411_04844_amd.build``);
+loading fails loudly otherwise -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+from .inputs import Geometry, GridSpec
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdgr.so")
+
+DGR_OK = 0
+STATUS = {0: "ok", 1: "invalid argument", 2: "workspace", 3: "capacity", 4: "hip"}
+
+
+class DgrError(RuntimeError):
+    def __init__(self, fn, status, detail):
+        super().__init__(f"{fn}: {STATUS.get(status, status)}: {detail}")
+        self.status = status
+
+
+class DgrGrid(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32 * 3), ("lo", ctypes.c_float * 3),
+                ("inv_h", ctypes.c_float * 3)]
+
+
+class DgrTrunc(ctypes.Structure):
+    _fields_ = [("k_sigma", ctypes.c_float), ("box_half", ctypes.c_int32)]
+
+
+class DgrGeometry(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_views", ctypes.c_int32), ("nu", ctypes.c_int32),
+                ("nv", ctypes.c_int32), ("views", ctypes.c_void_p), ("step", ctypes.c_float),
+                ("length_scale", ctypes.c_float)]
+
+
+_lib = None
+_SIGS = {
+    "dgr_voxelize_workspace": (ctypes.c_size_t, ["i64", "i64", "grid"]),
+    "dgr_voxelize_plan": ("st", ["p", "p", "p", "i64", "grid", "trunc", "p", "p", "sz", "p"]),
+    "dgr_voxelize": ("st", ["p", "p", "p", "p", "i64", "grid", "trunc", "p", "p", "sz", "p"]),
+    "dgr_voxelize_backward_workspace": (ctypes.c_size_t, ["i64"]),
+    "dgr_voxelize_backward": ("st", ["p", "p", "p", "p", "i64", "grid", "trunc", "p", "p", "p",
+                                     "p", "p", "p", "sz", "p"]),
+    "dgr_project_workspace": (ctypes.c_size_t, ["grid", "geom"]),
+    "dgr_project": ("st", ["p", "grid", "geom", "p", "p", "sz", "p"]),
+    "dgr_project_l1": ("st", ["p", "grid", "geom", "p", "p", "p", "p", "sz", "p"]),
+    "dgr_backproject": ("st", ["p", "grid", "geom", "p", "p", "sz", "p"]),
+    "dgr_adam": ("st", ["p", "p", "p", "p", "i64", "f32", "f32", "f32", "f32", "i64", "p"]),
+    "dgr_bbox": ("st", ["p", "p", "p", "i64", "grid", "trunc", "p", "p"]),
+    "dgr_bin": ("st", ["p", "p", "p", "i64", "grid", "trunc", "p", "p", "p", "sz", "p"]),
+    "dgr_check": ("st", ["p", "p"]),
+    "dgr_status_string": (ctypes.c_char_p, ["i32"]),
+    "dgr_last_error": (ctypes.c_char_p, []),
+    "dgr_version": (ctypes.c_int32, []),
+}
+_CT = {"p": ctypes.c_void_p, "i64": ctypes.c_int64, "i32": ctypes.c_int32, "f32": ctypes.c_float,
+       "sz": ctypes.c_size_t, "grid": ctypes.POINTER(DgrGrid), "trunc": ctypes.POINTER(DgrTrunc),
+       "geom": ctypes.POINTER(DgrGeometry), "st": ctypes.c_int}
+
+
+def lib():
+    """Load libdgr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"{_LIB_PATH} is missing: build it with "
+                               "`python -m paper_2411_04844_amd.build` (no fallback exists)")
+        L = ctypes.CDLL(_LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = _CT[res] if isinstance(res, str) else res
+            f.argtypes = [_CT[a] for a in args]
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _check(fn, st):
+    if st != DGR_OK:
+        raise DgrError(fn, st, lib().dgr_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need(t, dtype, shape=None, name="tensor"):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous {dtype} GPU tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+def c_grid(grid: GridSpec) -> DgrGrid:
+    g = DgrGrid()
+    for a in range(3):
+        g.dims[a], g.lo[a], g.inv_h[a] = grid.dims[a], grid.lo[a], grid.inv_h[a]
+    return g
+
+
+def c_trunc(k_sigma=3.0, box_half=8) -> DgrTrunc:
+    return DgrTrunc(float(k_sigma), int(box_half))
+
+
+def c_geom(geom: Geometry, views_dev: torch.Tensor) -> DgrGeometry:
+    _need(views_dev, torch.float32, (geom.n_views, 12), "views")
+    return DgrGeometry(geom.kind, geom.n_views, geom.nu, geom.nv, views_dev.data_ptr(),
+                       float(geom.step), float(geom.length_scale))
+
+
+class Workspace:
+    """A zero-initialised, 256-byte-aligned device buffer that grows on demand."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.buf = None
+
+    def get(self, nbytes: int) -> torch.Tensor:
+        nbytes = max(int(nbytes), 256)
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = torch.zeros(nbytes + 256, dtype=torch.uint8, device=self.device)
+        return self.buf
+
+    def ptr_size(self, nbytes):
+        b = self.get(nbytes)
+        base = b.data_ptr()
+        off = (-base) % 256
+        return ctypes.c_void_p(base + off), b.numel() - off
+
+
+# --------------------------------------------------------------------------
+# entry points
+# --------------------------------------------------------------------------
+def dgr_voxelize_workspace(n, max_pairs, grid: GridSpec) -> int:
+    g = c_grid(grid)
+    return int(lib().dgr_voxelize_workspace(int(n), int(max_pairs), ctypes.byref(g)))
+
+
+def dgr_voxelize_plan(mu, scale, quat, grid: GridSpec, k_sigma=3.0, box_half=8, ws=None) -> int:
+    n = mu.shape[0]
+    ws = ws or Workspace(mu.device)
+    p, sz = ws.ptr_size(dgr_voxelize_workspace(n, 0, grid))
+    out = ctypes.c_int64(0)
+    g, t = c_grid(grid), c_trunc(k_sigma, box_half)
+    _check("dgr_voxelize_plan", lib().dgr_voxelize_plan(
+        _ptr(mu), _ptr(scale), _ptr(quat), n, ctypes.byref(g), ctypes.byref(t), ctypes.byref(out),
+        p, sz, _stream()))
+    return int(out.value)
+
+
+def dgr_voxelize(mu, scale, quat, density, grid: GridSpec, k_sigma=3.0, box_half=8, out=None,
+                 ws: Workspace | None = None, max_pairs: int | None = None):
+    n = mu.shape[0]
+    for name, t, c in (("mu", mu, 3), ("scale", scale, 3), ("quat", quat, 4)):
+        _need(t, torch.float32, (n, c), name)
+    _need(density, torch.float32, (n,), "density")
+    if out is None:
+        out = torch.empty(grid.shape, dtype=torch.float32, device=mu.device)
+    _need(out, torch.float32, grid.shape, "out")
+    ws = ws or Workspace(mu.device)
+    if max_pairs is None:
+        max_pairs = dgr_voxelize_plan(mu, scale, quat, grid, k_sigma, box_half, ws)
+    p, sz = ws.ptr_size(dgr_voxelize_workspace(n, max_pairs, grid))
+    g, t = c_grid(grid), c_trunc(k_sigma, box_half)
+    _check("dgr_voxelize", lib().dgr_voxelize(
+        _ptr(mu), _ptr(scale), _ptr(quat), _ptr(density), n, ctypes.byref(g), ctypes.byref(t),
+        _ptr(out), p, sz, _stream()))
+    return out
+
+
+def dgr_voxelize_backward(mu, scale, quat, density, dvolume, grid: GridSpec, k_sigma=3.0,
+                          box_half=8, ws: Workspace | None = None, outs=None):
+    n = mu.shape[0]
+    _need(dvolume, torch.float32, grid.shape, "dvolume")
+    if outs is None:
+        outs = (torch.empty_like(mu), torch.empty_like(scale), torch.empty_like(quat),
+                torch.empty_like(density))
+    ws = ws or Workspace(mu.device)
+    p, sz = ws.ptr_size(int(lib().dgr_voxelize_backward_workspace(n)))
+    g, t = c_grid(grid), c_trunc(k_sigma, box_half)
+    _check("dgr_voxelize_backward", lib().dgr_voxelize_backward(
+        _ptr(mu), _ptr(scale), _ptr(quat), _ptr(density), n, ctypes.byref(g), ctypes.byref(t),
+        _ptr(dvolume), *(_ptr(o) for o in outs), p, sz, _stream()))
+    return outs
+
+
+def dgr_project_workspace(grid: GridSpec, geom: Geometry, views_dev) -> int:
+    g, G = c_grid(grid), c_geom(geom, views_dev)
+    return int(lib().dgr_project_workspace(ctypes.byref(g), ctypes.byref(G)))
+
+
+def dgr_project(volume, grid: GridSpec, geom: Geometry, views_dev, out=None,
+                ws: Workspace | None = None):
+    _need(volume, torch.float32, grid.shape, "volume")
+    if out is None:
+        out = torch.empty((geom.n_views, geom.nv, geom.nu), dtype=torch.float32, device=volume.device)
+    _need(out, torch.float32, (geom.n_views, geom.nv, geom.nu), "out")
+    ws = ws or Workspace(volume.device)
+    g, G = c_grid(grid), c_geom(geom, views_dev)
+    p, sz = ws.ptr_size(lib().dgr_project_workspace(ctypes.byref(g), ctypes.byref(G)))
+    _check("dgr_project", lib().dgr_project(_ptr(volume), ctypes.byref(g), ctypes.byref(G),
+                                            _ptr(out), p, sz, _stream()))
+    return out
+
+
+def dgr_project_l1(volume, target, grid: GridSpec, geom: Geometry, views_dev, loss=None,
+                   dproj=None, ws: Workspace | None = None):
+    shape = (geom.n_views, geom.nv, geom.nu)
+    _need(volume, torch.float32, grid.shape, "volume")
+    _need(target, torch.float32, shape, "target")
+    if loss is None:
+        loss = torch.empty((), dtype=torch.float32, device=volume.device)
+    if dproj is None:
+        dproj = torch.empty(shape, dtype=torch.float32, device=volume.device)
+    ws = ws or Workspace(volume.device)
+    g, G = c_grid(grid), c_geom(geom, views_dev)
+    p, sz = ws.ptr_size(lib().dgr_project_workspace(ctypes.byref(g), ctypes.byref(G)))
+    _check("dgr_project_l1", lib().dgr_project_l1(
+        _ptr(volume), ctypes.byref(g), ctypes.byref(G), _ptr(target), _ptr(loss), _ptr(dproj), p, sz,
+        _stream()))
+    return loss, dproj
+
+
+def dgr_backproject(proj, grid: GridSpec, geom: Geometry, views_dev, out=None,
+                    ws: Workspace | None = None):
+    _need(proj, torch.float32, (geom.n_views, geom.nv, geom.nu), "proj")
+    if out is None:
+        out = torch.empty(grid.shape, dtype=torch.float32, device=proj.device)
+    _need(out, torch.float32, grid.shape, "out")
+    ws = ws or Workspace(proj.device)
+    g, G = c_grid(grid), c_geom(geom, views_dev)
+    p, sz = ws.ptr_size(lib().dgr_project_workspace(ctypes.byref(g), ctypes.byref(G)))
+    _check("dgr_backproject", lib().dgr_backproject(_ptr(proj), ctypes.byref(g), ctypes.byref(G),
+                                                    _ptr(out), p, sz, _stream()))
+    return out
+
+
+def dgr_adam(param, grad, m, v, lr, step, b1=0.9, b2=0.999, eps=1e-8):
+    for name, t in (("param", param), ("grad", grad), ("m", m), ("v", v)):
+        _need(t, torch.float32, param.shape, name)
+    _check("dgr_adam", lib().dgr_adam(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), param.numel(),
+                                       float(lr), float(b1), float(b2), float(eps), int(step),
+                                       _stream()))
+
+
+def dgr_bbox(mu, scale, quat, grid: GridSpec, k_sigma=3.0, box_half=8):
+    n = mu.shape[0]
+    box = torch.empty((n, 6), dtype=torch.int32, device=mu.device)
+    g, t = c_grid(grid), c_trunc(k_sigma, box_half)
+    _check("dgr_bbox", lib().dgr_bbox(_ptr(mu), _ptr(scale), _ptr(quat), n, ctypes.byref(g),
+                                      ctypes.byref(t), _ptr(box), _stream()))
+    return box
+
+
+def dgr_bin(mu, scale, quat, grid: GridSpec, k_sigma=3.0, box_half=8):
+    n = mu.shape[0]
+    ws = Workspace(mu.device)
+    P = dgr_voxelize_plan(mu, scale, quat, grid, k_sigma, box_half, ws)
+    T = 1
+    for d in grid.dims:
+        T *= (d + 7) // 8
+    pairs = torch.empty((max(P, 1), 2), dtype=torch.int32, device=mu.device)
+    tb = torch.empty(T + 1, dtype=torch.int32, device=mu.device)
+    p, sz = ws.ptr_size(dgr_voxelize_workspace(n, P, grid))
+    g, t = c_grid(grid), c_trunc(k_sigma, box_half)
+    _check("dgr_bin", lib().dgr_bin(_ptr(mu), _ptr(scale), _ptr(quat), n, ctypes.byref(g),
+                                    ctypes.byref(t), _ptr(pairs), _ptr(tb), p, sz, _stream()))
+    return pairs[:P], tb
+
+
+def dgr_check(ws: Workspace):
+    p, _ = ws.ptr_size(256)
+    _check("dgr_check", lib().dgr_check(p, _stream()))

@@ -1,0 +1,94 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry
+point declared in include/dgr.h, and rejects bad arguments on the host
+before launching anything."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2411_04844_amd import inputs, native
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "dgr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dgr_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    L = native.lib()
+    names = _declared()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(native.exported_symbols())
+
+
+def test_version_and_status_strings():
+    L = native.lib()
+    assert L.dgr_version() == 1
+    assert L.dgr_status_string(0) == b"ok"
+    assert L.dgr_status_string(3) == b"pair capacity exceeded"
+
+
+def _grid(dims=(64, 64, 64)):
+    return native.c_grid(inputs.GridSpec(dims, (-1.0, -1.0, -1.0), (32.0, 32.0, 32.0)))
+
+
+def test_workspace_sizes_grow_with_pairs_and_reject_bad_args():
+    L = native.lib()
+    g = _grid()
+    a = L.dgr_voxelize_workspace(1000, 0, ctypes.byref(g))
+    b = L.dgr_voxelize_workspace(1000, 100000, ctypes.byref(g))
+    assert 0 < a < b
+    assert b - a >= 100000 * 16
+    assert L.dgr_voxelize_workspace(-1, 0, ctypes.byref(g)) == 0
+    bad = _grid((0, 64, 64))
+    assert L.dgr_voxelize_workspace(10, 0, ctypes.byref(bad)) == 0
+    assert L.dgr_voxelize_backward_workspace(100) >= 100 * 64
+
+
+def test_host_validation_returns_status_without_launch():
+    L = native.lib()
+    g, t = _grid(), native.c_trunc()
+    fake = ctypes.c_void_p(0x10000)
+    # null grid
+    assert L.dgr_voxelize(fake, fake, fake, fake, 10, None, ctypes.byref(t), fake, fake, 1 << 20, None) == 1
+    assert b"grid" in L.dgr_last_error()
+    # misaligned workspace
+    st = L.dgr_voxelize(fake, fake, fake, fake, 10, ctypes.byref(g), ctypes.byref(t), fake,
+                        ctypes.c_void_p(0x10001), 1 << 20, None)
+    assert st == 2 and b"aligned" in L.dgr_last_error()
+    # workspace too small
+    st = L.dgr_voxelize(fake, fake, fake, fake, 10, ctypes.byref(g), ctypes.byref(t), fake, fake, 64, None)
+    assert st == 2
+    # bad geometry
+    geom = native.DgrGeometry(7, 1, 8, 8, 0x10000, 0.1, 1.0)
+    assert L.dgr_project(fake, ctypes.byref(g), ctypes.byref(geom), fake, fake, 1 << 30, None) == 1
+    geom = native.DgrGeometry(1, 1, 8, 8, 0x10000, 0.0, 1.0)
+    assert L.dgr_project(fake, ctypes.byref(g), ctypes.byref(geom), fake, fake, 1 << 30, None) == 1
+    # step so small that a ray would take more than 2^20 samples
+    geom = native.DgrGeometry(1, 1, 8, 8, 0x10000, 1e-7, 1.0)
+    assert L.dgr_project(fake, ctypes.byref(g), ctypes.byref(geom), fake, fake, 1 << 30, None) == 1
+    assert b"step" in L.dgr_last_error()
+    # Adam hyper-parameters
+    assert L.dgr_adam(fake, fake, fake, fake, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None) == 1
+    assert L.dgr_adam(fake, fake, fake, fake, 10, 1e-3, 1.5, 0.999, 1e-8, 1, None) == 1
+    # negative n
+    assert L.dgr_bbox(fake, fake, fake, -1, ctypes.byref(g), ctypes.byref(t), fake, None) == 1
+    # n == 0 is a no-op that succeeds without touching the device
+    assert L.dgr_bbox(None, None, None, 0, ctypes.byref(g), ctypes.byref(t), None, None) == 0
+    # truncation box_half out of range in fixed-cuboid mode
+    t2 = native.c_trunc(0.0, -3)
+    assert L.dgr_bbox(fake, fake, fake, 5, ctypes.byref(g), ctypes.byref(t2), fake, None) == 1
+
+
+def test_project_workspace_covers_padded_volume():
+    L = native.lib()
+    g = _grid((40, 30, 20))
+    geom = native.DgrGeometry(1, 3, 17, 9, 0x10000, 0.01, 1.0)
+    ws = L.dgr_project_workspace(ctypes.byref(g), ctypes.byref(geom))
+    assert ws >= 44 * 34 * 24 * 4
