@@ -168,6 +168,36 @@ dgr_status dgr_backproject(const float *proj, const dgr_grid *grid, const dgr_ge
 dgr_status dgr_adam(float *param, const float *grad, float *m, float *v, int64_t n, float lr,
                     float b1, float b2, float eps, int64_t step, void *stream);
 
+/* ---- binary64 path for finite-difference gradient checks ------------------ */
+
+/* The volume of dgr_voxelize evaluated in binary64 (parameters promoted
+ * exactly from binary32), volume [nz][ny][nx] binary64, overwritten.  Same
+ * boxes and workspace as dgr_voxelize. */
+size_t dgr_voxelize_f64_workspace(int64_t n, int64_t max_pairs, const dgr_grid *grid);
+dgr_status dgr_voxelize_f64(const float *mu, const float *scale, const float *quat,
+                            const float *density, int64_t n, const dgr_grid *grid,
+                            const dgr_trunc *trunc, double *volume, void *ws, size_t ws_bytes,
+                            void *stream);
+
+/* Finite differences of the mean-L1 projection loss (sec. 4.3) for n_jobs
+ * (Gaussian, component, step) jobs.  Component 0-2 = mean x,y,z, 3-5 = scale,
+ * 6-9 = quaternion w,x,y,z, 10 = density.  The job's Gaussian keeps its
+ * truncation box; only rays crossing it change, so the kernel sums, over
+ * those rays, |res + A dV| - |res| with res = A V - target computed in
+ * binary64 from `volume` (dgr_voxelize_f64) and dV the binary64 change of the
+ * Gaussian on its box for +h and -h.  out [n_jobs][n_views][2] (DEVICE,
+ * binary64): per-view sums for +h and -h; the loss changes are their sums
+ * over views divided by M = n_views*nu*nv.  job_gid, job_comp, job_h are HOST
+ * arrays.  box_cap bounds the voxels of any job's box (larger boxes give 0).
+ * Synchronises `stream`. */
+size_t dgr_fd_l1_f64_workspace(int64_t n, int32_t n_jobs, int64_t box_cap, const dgr_geometry *geom);
+dgr_status dgr_fd_l1_f64(const double *volume, const dgr_grid *grid, const dgr_geometry *geom,
+                         const float *target, const float *mu, const float *scale, const float *quat,
+                         const float *density, int64_t n, const dgr_trunc *trunc,
+                         const int32_t *job_gid, const int32_t *job_comp, const double *job_h,
+                         int32_t n_jobs, int64_t box_cap, double *out, void *ws, size_t ws_bytes,
+                         void *stream);
+
 /* ---- inspection ---------------------------------------------------------- */
 
 /* Truncation boxes int32 [n][6] = (lo_x, lo_y, lo_z, hi_x, hi_y, hi_z). */

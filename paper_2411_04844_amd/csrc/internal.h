@@ -86,6 +86,63 @@ inline DevGrid dev_grid(const dgr_grid *g) {
     return d;
 }
 
+// Inclusive detector rectangle (pixel indices, widened by one pixel) that
+// contains the shadow of the box [ulo, uhi] (continuous voxel coordinates) in
+// one view (`view` = the 12 floats of the view).  A box is convex, so its
+// shadow lies in the bounding rectangle of its projected corners.  If a corner
+// cannot be projected (behind a cone source, or a ray parallel to the
+// detector) the whole detector is returned.  An empty rectangle has iu0 > iu1.
+__device__ inline void shadow_rect(int kind, const float *view, int nu, int nv, const DevGrid &g,
+                                   const double ulo[3], const double uhi[3], int *iu0, int *iu1,
+                                   int *iv0, int *iv1) {
+    double A[3], D0[3], eu[3], ev[3];
+    for (int a = 0; a < 3; ++a) {
+        A[a] = view[a];
+        D0[a] = view[3 + a];
+        eu[a] = view[6 + a];
+        ev[a] = view[9 + a];
+    }
+    const double n[3] = {eu[1] * ev[2] - eu[2] * ev[1], eu[2] * ev[0] - eu[0] * ev[2],
+                         eu[0] * ev[1] - eu[1] * ev[0]};
+    const double uu = eu[0] * eu[0] + eu[1] * eu[1] + eu[2] * eu[2];
+    const double vv = ev[0] * ev[0] + ev[1] * ev[1] + ev[2] * ev[2];
+    const double uv = eu[0] * ev[0] + eu[1] * ev[1] + eu[2] * ev[2];
+    const double det2 = uu * vv - uv * uv;
+    double amin = 1e300, amax = -1e300, bmin = 1e300, bmax = -1e300;
+    bool ok = det2 > 0.0;
+    for (int c = 0; c < 8 && ok; ++c) {
+        double X[3], dir[3];
+        for (int a = 0; a < 3; ++a) {
+            const double u = ((c >> a) & 1) ? uhi[a] : ulo[a];
+            X[a] = (double)g.lo[a] + (u + 0.5) / (double)g.inv_h[a];
+            dir[a] = kind == DGR_PARALLEL ? A[a] : X[a] - A[a];
+        }
+        const double den = n[0] * dir[0] + n[1] * dir[1] + n[2] * dir[2];
+        if (!(fabs(den) > 1e-300)) { ok = false; break; }
+        const double t = (n[0] * (D0[0] - X[0]) + n[1] * (D0[1] - X[1]) + n[2] * (D0[2] - X[2])) / den;
+        if (kind == DGR_CONE && !(t > -1.0)) { ok = false; break; }  // corner behind the source
+        double P[3];
+        for (int a = 0; a < 3; ++a) P[a] = X[a] + t * dir[a] - D0[a];
+        const double pu = P[0] * eu[0] + P[1] * eu[1] + P[2] * eu[2];
+        const double pv = P[0] * ev[0] + P[1] * ev[1] + P[2] * ev[2];
+        const double ca = (pu * vv - pv * uv) / det2, cb = (pv * uu - pu * uv) / det2;
+        amin = fmin(amin, ca); amax = fmax(amax, ca);
+        bmin = fmin(bmin, cb); bmax = fmax(bmax, cb);
+    }
+    *iu0 = 0; *iu1 = nu - 1; *iv0 = 0; *iv1 = nv - 1;
+    if (ok) {
+        const double cu = 0.5 * (nu - 1), cv = 0.5 * (nv - 1);
+        const double a0 = floor(amin + cu) - 1.0, a1 = ceil(amax + cu) + 1.0;
+        const double b0 = floor(bmin + cv) - 1.0, b1 = ceil(bmax + cv) + 1.0;
+        if (a1 < 0.0 || b1 < 0.0 || a0 > nu - 1.0 || b0 > nv - 1.0) {
+            *iu0 = 1; *iu1 = 0; *iv0 = 1; *iv1 = 0;  // empty
+            return;
+        }
+        *iu0 = (int)fmax(0.0, a0); *iu1 = (int)fmin((double)(nu - 1), a1);
+        *iv0 = (int)fmax(0.0, b0); *iv1 = (int)fmin((double)(nv - 1), b1);
+    }
+}
+
 // Enqueue the prep kernel: records + tile counts (and optional int32 boxes).
 dgr_status launch_prep(const float *mu, const float *scale, const float *quat,
                        const float *density, int64_t n, const dgr_grid *grid,

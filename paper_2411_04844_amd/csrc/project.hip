@@ -9,14 +9,12 @@
 // outside the grid.
 //
 // Sample positions.  Per-ray set-up (direction, anchor, advance) runs in
-// binary64.  Sample k sits at u_k = I(kb) + (f(kb) + (k - kb) * du), where
-// kb = 32 * floor(k / 32), I(kb) is the integer part of the binary64 position
-// cu + kb * du and f(kb) its residual (the floor / residual split of the
-// paper's Discretize and Align step), and the bracket is evaluated in binary32.
-// The offsets stay below ~17 voxels, so positions are within ~2e-6 voxel of
-// exact on any grid, and the anchor depends only on (ray, k): the projector and
-// the backprojector evaluate every sample at the same position.
-//
+// binary64 and is then rounded to 64-bit fixed point with 32 fractional bits:
+// U_k = U_c + k * DU.  The integer part (high word) is the floor used for the
+// taps, the low word times 2^-32 is the trilinear weight.  Integer steps are
+// exact, so sample k has the same position in every kernel and every brick,
+// from any starting sample, and stays within ~5e-8 voxel of the binary64
+// position; no periodic re-anchoring is needed.
 // Forward: one thread per ray; the volume is read from a copy with a two-voxel
 // zero border, so the eight taps of any sample in the support need no test.
 // Backward: one work-group per 16^3-cell brick accumulates, over all views, the
@@ -35,7 +33,9 @@ namespace dgr {
 namespace {
 
 constexpr int kPad = 2;
-constexpr int kRayTile = 16;  // 16 x 16 detector pixels per work-group (forward)
+constexpr int kTileU = 64;  // forward work-group: 64 x 4 detector pixels, one row per wave
+constexpr int kTileV = 4;
+constexpr int kXcd = 8;     // MI355X: work-groups are dealt round-robin to 8 XCDs
 constexpr int kB = 16;        // brick edge in cells (backward)
 constexpr int kBT = kB + 1;   // brick tile edge in voxels
 constexpr int kBT3 = kBT * kBT * kBT;
@@ -73,17 +73,23 @@ inline Bricks bricks_of(const dgr_grid *g) {
     return b;
 }
 
+// Two zero-bordered copies: [z][y][x] (x fastest) and [z][x][y] (y fastest).
+// A view reads the copy whose fastest axis follows the detector's u axis, so
+// the 64 lanes of a wave (64 adjacent pixels of a detector row) walk along
+// contiguous memory whatever the view angle.
 __global__ __launch_bounds__(256) void pad_volume(const float *__restrict__ V, DevGrid g, PadDims p,
-                                                  float *__restrict__ out) {
+                                                  float *__restrict__ out, float *__restrict__ outT) {
     const int64_t total = p.plane * p.pz;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
         int64_t z = i / p.plane, rem = i - z * p.plane;
         int64_t y = rem / p.px, x = rem - y * p.px;
+        const int64_t iT = (z * p.px + x) * p.py + y;
         x -= kPad; y -= kPad; z -= kPad;
         float v = 0.0f;
         if (x >= 0 && y >= 0 && z >= 0 && x < g.nx && y < g.ny && z < g.nz)
             v = V[(z * g.ny + y) * g.nx + x];
         out[i] = v;
+        outT[iT] = v;
     }
 }
 
@@ -97,7 +103,14 @@ struct GeomDev {
 struct Ray {
     double cu[3];  // padded voxel coordinate of the anchor c
     double du[3];  // voxel-coordinate advance per sample
+    long long U[3];   // cu in 32.32 fixed point
+    long long DU[3];  // du in 32.32 fixed point
 };
+
+constexpr double kTwo32 = 4294967296.0;
+constexpr float kInv32 = 2.3283064365386963e-10f;  // 2^-32
+constexpr double kMaxK = 4194304.0;                 // |k| limit (2^22) for fixed-point exactness
+
 
 // Unit direction and anchor of the ray through pixel (iu, iv) of view j, in
 // binary64.  1/|d| comes from the hardware estimate refined by two Newton steps.
@@ -130,6 +143,11 @@ __device__ __forceinline__ void ray_geom(const GeomDev &G, const DevGrid &g, int
         const double c = o[a] - od * d[a];
         r.cu[a] = (c - (double)g.lo[a]) * (double)g.inv_h[a] + (kPad - 0.5);
         r.du[a] = d[a] * ((double)g.inv_h[a] * G.step);
+        // |cu| < 2^30 keeps U and every in-range position below 2^62 (the
+        // caller treats larger anchors as misses through k_interval's guard)
+        const double cu_c = fmin(fmax(r.cu[a], -1073741824.0), 1073741824.0);
+        r.U[a] = __double2ll_rn(cu_c * kTwo32);
+        r.DU[a] = __double2ll_rn(r.du[a] * kTwo32);
     }
 }
 
@@ -148,11 +166,49 @@ __device__ bool k_interval(const Ray &r, const double lo[3], const double hi[3],
         tmax = fmin(tmax, fmax(t0, t1));
     }
     const double kk0 = ceil(tmin), kk1 = floor(tmax);
-    // Supports beyond +-2^30 samples of the anchor are treated as misses.
-    if (!(kk0 <= kk1) || kk0 < -1073741824.0 || kk1 > 1073741824.0) return false;
+    // Samples beyond +-2^22 of the anchor, or anchors beyond 2^30 voxels, are
+    // treated as misses (absurdly placed grids); this keeps the fixed-point
+    // positions within 2^-10 voxel of the binary64 ones.
+    if (!(kk0 <= kk1) || kk0 < -kMaxK || kk1 > kMaxK) return false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        if (!(fabs(r.cu[a]) < 1073741824.0)) return false;
     *k0 = (int)kk0;
     *k1 = (int)kk1;
     return true;
+}
+
+// A superset of the samples with lo <= u_a <= hi, from binary32 reciprocals and
+// widened by one sample on each side; callers test every sample exactly.
+__device__ bool k_interval_coarse(const Ray &r, const double lo[3], const double hi[3], int *k0,
+                                  int *k1) {
+    float tmin = -3.0e38f, tmax = 3.0e38f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float du = (float)r.du[a];
+        // offsets from the anchor in binary64, then rounded: t keeps ~2e-7
+        // relative accuracy however large the offsets are
+        const float o0 = (float)(lo[a] - r.cu[a]), o1 = (float)(hi[a] - r.cu[a]);
+        if (du == 0.0f) {
+            if (!(o0 <= 1.0f && o1 >= -1.0f)) return false;
+            continue;
+        }
+        const float inv = __builtin_amdgcn_rcpf(du);
+        const float t0 = o0 * inv, t1 = o1 * inv;
+        tmin = fmaxf(tmin, fminf(t0, t1));
+        tmax = fminf(tmax, fmaxf(t0, t1));
+    }
+    // relative error of the binary32 interval is below 1e-6 of |t|
+    const float slack = 1.0f + 2e-6f * fmaxf(fabsf(tmin), fabsf(tmax));
+    tmin -= slack;
+    tmax += slack;
+    if (!(tmin <= tmax) || tmin < -(float)kMaxK || tmax > (float)kMaxK) return false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        if (!(fabs(r.cu[a]) < 1073741824.0)) return false;
+    *k0 = (int)ceilf(tmin);
+    *k1 = (int)floorf(tmax);
+    return *k0 <= *k1;
 }
 
 __device__ __forceinline__ bool support_range(const Ray &r, const DevGrid &g, int *k0, int *k1) {
@@ -162,63 +218,64 @@ __device__ __forceinline__ bool support_range(const Ray &r, const DevGrid &g, in
     return k_interval(r, lo, hi, k0, k1);
 }
 
-constexpr int kSeg = 32;  // samples per re-anchored segment (a power of two)
-
-__device__ __forceinline__ void seg_base(const Ray &r, int kb, int ib[3], float bf[3]) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const double u = r.cu[a] + (double)kb * r.du[a];
-        const double f = floor(u);
-        ib[a] = (int)f;
-        bf[a] = (float)(u - f);
-    }
-}
-
 typedef float f2u __attribute__((ext_vector_type(2), aligned(4)));
 
 __device__ __forceinline__ f2u ld2(const float *p) { return *reinterpret_cast<const f2u *>(p); }
 
-// The floors are clamped so that every tap stays inside the padded volume: a
-// no-op for every sample of the support (whose taps lie in [0, dims + 3]); it
-// only guards the buffer against non-finite geometry.
+// Every sample of the support range has its floor in [0, dims + 2] (padded),
+// because the fixed-point position is within 2^-10 voxel of the binary64 one
+// that defined the range; its eight taps are therefore inside the padded copy.
 
-__device__ float march(const float *__restrict__ vp, const PadDims &p, const Ray &r, int k0, int k1) {
-    const float dux = (float)r.du[0], duy = (float)r.du[1], duz = (float)r.du[2];
-    const int px = p.px;
+// SWAP = 0 reads the [z][y][x] copy, SWAP = 1 the [z][x][y] copy.  The wave
+// steps through the common range [kw0, kw1] of its lanes' samples, so at every
+// step its 64 rays (adjacent pixels of a detector row) sit at the same depth
+// and their taps share cache lines; a lane reads only its own range [k0, k1].
+template <int SWAP>
+__device__ float march(const float *__restrict__ vp, const PadDims &p, const Ray &r, int k0, int k1,
+                       int kw0, int kw1) {
+    const int fa = SWAP ? 1 : 0, ma = SWAP ? 0 : 1;  // fastest and middle axes
+    const int row = SWAP ? p.py : p.px;              // stride of the middle axis
+    const int mid = SWAP ? p.px : p.py;              // extent of the middle axis
     const int plane = (int)p.plane;
+    long long uf = r.U[fa] + (long long)kw0 * r.DU[fa];
+    long long um = r.U[ma] + (long long)kw0 * r.DU[ma];
+    long long uz = r.U[2] + (long long)kw0 * r.DU[2];
+    const long long df = r.DU[fa], dm = r.DU[ma], dz = r.DU[2];
     float acc = 0.0f;
-    for (int k = k0; k <= k1;) {
-        const int kb = k & ~(kSeg - 1);
-        const int kend = min(kb + kSeg - 1, k1);
-        int ib[3];
-        float b[3];
-        seg_base(r, kb, ib, b);
-        // relative clamp bounds keep every absolute floor in [0, dims + 2]
-        const float lx = (float)(-ib[0]), ly = (float)(-ib[1]), lz = (float)(-ib[2]);
-        const float hx = (float)(p.px - 2 - ib[0]), hy = (float)(p.py - 2 - ib[1]),
-                    hz = (float)(p.pz - 2 - ib[2]);
-        const float *vb = vp + (((int64_t)ib[2] * p.py + ib[1]) * px + ib[0]);
-        for (int m = k - kb; m <= kend - kb; ++m) {
-            const float fm = (float)m;
-            const float ux = fmaf(fm, dux, b[0]), uy = fmaf(fm, duy, b[1]), uz = fmaf(fm, duz, b[2]);
-            const float flx = __builtin_amdgcn_fmed3f(floorf(ux), lx, hx);
-            const float fly = __builtin_amdgcn_fmed3f(floorf(uy), ly, hy);
-            const float flz = __builtin_amdgcn_fmed3f(floorf(uz), lz, hz);
-            const float wx = ux - flx, wy = uy - fly, wz = uz - flz;
-            const int idx = ((int)flz * p.py + (int)fly) * px + (int)flx;
-            const f2u a00 = ld2(vb + idx), a10 = ld2(vb + idx + px);
-            const f2u a01 = ld2(vb + idx + plane), a11 = ld2(vb + idx + plane + px);
-            const float c00 = fmaf(wx, a00.y - a00.x, a00.x);
-            const float c10 = fmaf(wx, a10.y - a10.x, a10.x);
-            const float c01 = fmaf(wx, a01.y - a01.x, a01.x);
-            const float c11 = fmaf(wx, a11.y - a11.x, a11.x);
-            const float c0 = fmaf(wy, c10 - c00, c00);
-            const float c1 = fmaf(wy, c11 - c01, c01);
+    for (int k = kw0; k <= kw1; ++k) {
+        if (k >= k0 && k <= k1) {
+            const int i_f = (int)(uf >> 32), i_m = (int)(um >> 32), iz = (int)(uz >> 32);
+            const float wf = (float)(unsigned)uf * kInv32;
+            const float wm = (float)(unsigned)um * kInv32;
+            const float wz = (float)(unsigned)uz * kInv32;
+            const int idx = (iz * mid + i_m) * row + i_f;
+            const f2u a00 = ld2(vp + idx), a10 = ld2(vp + idx + row);
+            const f2u a01 = ld2(vp + idx + plane), a11 = ld2(vp + idx + plane + row);
+            const float c00 = fmaf(wf, a00.y - a00.x, a00.x);
+            const float c10 = fmaf(wf, a10.y - a10.x, a10.x);
+            const float c01 = fmaf(wf, a01.y - a01.x, a01.x);
+            const float c11 = fmaf(wf, a11.y - a11.x, a11.x);
+            const float c0 = fmaf(wm, c10 - c00, c00);
+            const float c1 = fmaf(wm, c11 - c01, c01);
             acc += fmaf(wz, c1 - c0, c0);
         }
-        k = kend + 1;
+        uf += df;
+        um += dm;
+        uz += dz;
     }
     return acc;
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -228,28 +285,41 @@ __device__ __forceinline__ float wave_sum(float v) {
 }
 
 // mode 0: write P_hat; mode 1: fused L1 (loss partial per work-group + dproj).
+// Work-groups are numbered so that each XCD (which receives every 8th
+// dispatched work-group) runs a contiguous range of tiles: neighbouring
+// detector rows of the same view share that XCD's L2.
 template <int MODE>
-__global__ __launch_bounds__(256) void project_rays(const float *__restrict__ vp, PadDims p, DevGrid g,
-                                                    GeomDev G, int tiles_u, int tiles_v,
+__global__ __launch_bounds__(256) void project_rays(const float *__restrict__ vp,
+                                                    const float *__restrict__ vpT, PadDims p, DevGrid g,
+                                                    GeomDev G, int tiles_u, int tiles_v, int64_t nb,
                                                     const float *__restrict__ target,
                                                     float *__restrict__ out, float inv_m,
                                                     float *__restrict__ partial) {
-    const int64_t b = blockIdx.x;
+    const int64_t per_xcd = (nb + kXcd - 1) / kXcd;
+    const int64_t b = (int64_t)(blockIdx.x % kXcd) * per_xcd + blockIdx.x / kXcd;
+    if (b >= nb) return;
     const int per_view = tiles_u * tiles_v;
     const int j = (int)(b / per_view);
     const int rem = (int)(b - (int64_t)j * per_view);
     const int tv = rem / tiles_u, tu = rem - tv * tiles_u;
-    const int iu = tu * kRayTile + (threadIdx.x & (kRayTile - 1));
-    const int iv = tv * kRayTile + (threadIdx.x / kRayTile);
+    const int iu = tu * kTileU + (threadIdx.x & (kTileU - 1));
+    const int iv = tv * kTileV + (threadIdx.x / kTileU);
     const bool live = iu < G.nu && iv < G.nv;
+    // fastest axis of the copy to read: the one the detector's u axis follows
+    const float *eu = G.views + 12 * (int64_t)j + 6;
+    const bool swap = fabsf(eu[1] * g.inv_h[1]) > fabsf(eu[0] * g.inv_h[0]);
     float val = 0.0f;
+    Ray r;
+    int k0 = 0, k1 = -1;
+    bool ok = false;
     if (live) {
-        Ray r;
         ray_geom(G, g, j, iu, iv, r);
-        int k0, k1;
-        if (support_range(r, g, &k0, &k1)) val = march(vp, p, r, k0, k1);
-        val *= G.scale;
+        ok = support_range(r, g, &k0, &k1);
     }
+    const int kw0 = __builtin_amdgcn_readfirstlane(wave_min(ok ? k0 : 0x7fffffff));
+    const int kw1 = __builtin_amdgcn_readfirstlane(wave_max(ok ? k1 : -0x7fffffff));
+    if (ok) val = swap ? march<1>(vpT, p, r, k0, k1, kw0, kw1) : march<0>(vp, p, r, k0, k1, kw0, kw1);
+    val *= G.scale;
     const int64_t ri = ((int64_t)j * G.nv + iv) * G.nu + iu;
     if (MODE == 0) {
         if (live) out[ri] = val;
@@ -285,11 +355,8 @@ __global__ __launch_bounds__(256) void finish_loss(const float *__restrict__ par
 
 // ---- backprojection ---------------------------------------------------------
 
-// Detector rectangle (pixel indices, inclusive, widened by one pixel) that
-// contains the shadow of every brick's cell box, per (brick, view).  A box is
-// convex, so its shadow lies in the bounding rectangle of its eight projected
-// corners.  If a corner cannot be projected (behind the source, or a ray
-// parallel to the detector) the whole detector is used.
+// Detector rectangle that contains the shadow of each brick's cell box, per
+// (brick, view) (see shadow_rect).
 __global__ __launch_bounds__(256) void brick_rects(GeomDev G, DevGrid g, Bricks bk,
                                                    ushort4 *__restrict__ rect) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -298,56 +365,12 @@ __global__ __launch_bounds__(256) void brick_rects(GeomDev G, DevGrid g, Bricks 
     const int j = (int)(i / nb);
     const int64_t b = i - (int64_t)j * nb;
     const int bx = (int)(b % bk.nx), by = (int)((b / bk.nx) % bk.ny), bz = (int)(b / ((int64_t)bk.nx * bk.ny));
-    const int cb[3] = {bx * kB - 1, by * kB - 1, bz * kB - 1};
-    const float *v = G.views + 12 * (int64_t)j;
-    double A[3], D0[3], eu[3], ev[3];
-    for (int a = 0; a < 3; ++a) {
-        A[a] = v[a];
-        D0[a] = v[3 + a];
-        eu[a] = v[6 + a];
-        ev[a] = v[9 + a];
-    }
-    const double n[3] = {eu[1] * ev[2] - eu[2] * ev[1], eu[2] * ev[0] - eu[0] * ev[2],
-                         eu[0] * ev[1] - eu[1] * ev[0]};
-    const double uu = eu[0] * eu[0] + eu[1] * eu[1] + eu[2] * eu[2];
-    const double vv = ev[0] * ev[0] + ev[1] * ev[1] + ev[2] * ev[2];
-    const double uv = eu[0] * ev[0] + eu[1] * ev[1] + eu[2] * ev[2];
-    const double det2 = uu * vv - uv * uv;
-    double amin = 1e300, amax = -1e300, bmin = 1e300, bmax = -1e300;
-    bool ok = det2 > 0.0;
-    for (int c = 0; c < 8 && ok; ++c) {
-        double X[3];
-        for (int a = 0; a < 3; ++a) {
-            const double ucell = (double)(cb[a] + (((c >> a) & 1) ? kB : 0));  // cell box corner, u
-            X[a] = (double)g.lo[a] + (ucell + 0.5) / (double)g.inv_h[a];
-        }
-        double dir[3], P[3];
-        if (G.kind == DGR_PARALLEL) {
-            for (int a = 0; a < 3; ++a) dir[a] = A[a];
-        } else {
-            for (int a = 0; a < 3; ++a) dir[a] = X[a] - A[a];
-        }
-        const double den = n[0] * dir[0] + n[1] * dir[1] + n[2] * dir[2];
-        if (!(fabs(den) > 1e-300)) { ok = false; break; }
-        const double num = n[0] * (D0[0] - X[0]) + n[1] * (D0[1] - X[1]) + n[2] * (D0[2] - X[2]);
-        const double t = num / den;
-        if (G.kind == DGR_CONE && !(t > -1.0)) { ok = false; break; }  // corner behind the source
-        for (int a = 0; a < 3; ++a) P[a] = X[a] + t * dir[a] - D0[a];
-        const double pu = P[0] * eu[0] + P[1] * eu[1] + P[2] * eu[2];
-        const double pv = P[0] * ev[0] + P[1] * ev[1] + P[2] * ev[2];
-        const double ca = (pu * vv - pv * uv) / det2, cbv = (pv * uu - pu * uv) / det2;
-        amin = fmin(amin, ca); amax = fmax(amax, ca);
-        bmin = fmin(bmin, cbv); bmax = fmax(bmax, cbv);
-    }
-    int iu0 = 0, iu1 = G.nu - 1, iv0 = 0, iv1 = G.nv - 1;
-    if (ok) {
-        const double cu = 0.5 * (G.nu - 1), cv = 0.5 * (G.nv - 1);
-        iu0 = (int)fmax(0.0, floor(amin + cu) - 1.0);
-        iu1 = (int)fmin((double)(G.nu - 1), ceil(amax + cu) + 1.0);
-        iv0 = (int)fmax(0.0, floor(bmin + cv) - 1.0);
-        iv1 = (int)fmin((double)(G.nv - 1), ceil(bmax + cv) + 1.0);
-        if (iu0 > iu1 || iv0 > iv1) { iu0 = 1; iu1 = 0; iv0 = 1; iv1 = 0; }  // empty
-    }
+    // the brick's cells span voxel coordinates [c0, c0 + kB] (unpadded)
+    const double ulo[3] = {(double)(bx * kB - 1), (double)(by * kB - 1), (double)(bz * kB - 1)};
+    const double uhi[3] = {ulo[0] + kB, ulo[1] + kB, ulo[2] + kB};
+    int iu0, iu1, iv0, iv1;
+    shadow_rect(G.kind, G.views + 12 * (int64_t)j, G.nu, G.nv, g, ulo, uhi, &iu0, &iu1, &iv0, &iv1);
+    if (iu0 > iu1 || iv0 > iv1) { iu0 = 1; iu1 = 0; iv0 = 1; iv1 = 0; }
     rect[i] = make_ushort4((unsigned short)iu0, (unsigned short)iu1, (unsigned short)iv0, (unsigned short)iv1);
 }
 
@@ -390,8 +413,8 @@ __global__ __launch_bounds__(256) void backproject_bricks(const float *__restric
     // brick cells in padded coordinates: [c0, c0 + kB)
     const int c0x = bx * kB - 1 + kPad, c0y = by * kB - 1 + kPad, c0z = bz * kB - 1 + kPad;
     // The candidate k-range is exact in binary64 for the brick grown by eps, a
-    // bound on |binary32 position - binary64 position|; the cell test on the
-    // binary32 position then assigns every sample to exactly one brick.
+    // bound on |fixed-point position - binary64 position|; the cell test on the
+    // fixed-point position then assigns every sample to exactly one brick.
     const double blo[3] = {c0x - (double)eps, c0y - (double)eps, c0z - (double)eps};
     const double bhi[3] = {c0x + kB + (double)eps, c0y + kB + (double)eps, c0z + kB + (double)eps};
     const float gs = G.scale * fixed_scale(maxbits, G.scale);  // |proj * gs| < 2^30
@@ -401,45 +424,45 @@ __global__ __launch_bounds__(256) void backproject_bricks(const float *__restric
         const ushort4 rc = rect[(int64_t)j * nb + b];
         const int nu_r = (int)rc.y - (int)rc.x + 1, nv_r = (int)rc.w - (int)rc.z + 1;
         const int ncand = (nu_r > 0 && nv_r > 0) ? nu_r * nv_r : 0;
-        for (int c = t; c < ncand; c += 256) {
+        // Each thread takes a contiguous run of candidates, so the rays that a
+        // wave processes at the same time are several pixels apart and rarely
+        // add into the same LDS word.
+        const int per = (ncand + 255) / 256;
+        for (int i = 0; i < per; ++i) {
+            const int c = t * per + i;
+            if (c >= ncand) break;
             const int iv = (int)rc.z + c / nu_r, iu = (int)rc.x + c % nu_r;
             const float gr = gs * proj[((int64_t)j * G.nv + iv) * G.nu + iu];
             if (gr == 0.0f) continue;
             Ray r;
             ray_geom(G, g, j, iu, iv, r);
             int k0, k1;
-            if (!k_interval(r, blo, bhi, &k0, &k1)) continue;
-            const float dux = (float)r.du[0], duy = (float)r.du[1], duz = (float)r.du[2];
-            for (int k = k0; k <= k1;) {
-                const int kb = k & ~(kSeg - 1);
-                const int kend = min(kb + kSeg - 1, k1);
-                int ib[3];
-                float bs[3];
-                seg_base(r, kb, ib, bs);
-                const int ox = c0x - ib[0], oy = c0y - ib[1], oz = c0z - ib[2];
-                for (int m = k - kb; m <= kend - kb; ++m) {
-                    const float fm = (float)m;
-                    const float ux = fmaf(fm, dux, bs[0]), uy = fmaf(fm, duy, bs[1]), uz = fmaf(fm, duz, bs[2]);
-                    const float flx = floorf(ux), fly = floorf(uy), flz = floorf(uz);
-                    const int lx = (int)flx - ox, ly = (int)fly - oy, lz = (int)flz - oz;
-                    if ((unsigned)lx >= (unsigned)kB || (unsigned)ly >= (unsigned)kB ||
-                        (unsigned)lz >= (unsigned)kB)
-                        continue;
-                    const float wx = ux - flx, wy = uy - fly, wz = uz - flz;
-                    const float z1 = gr * wz, z0 = gr - z1;
-                    const float y01 = z0 * wy, y00 = z0 - y01, y11 = z1 * wy, y10 = z1 - y11;
-                    const float a0 = y00 * wx, a1 = y01 * wx, a2 = y10 * wx, a3 = y11 * wx;
-                    unsigned long long *q = tile + (lz * kBT + ly) * kBT + lx;
-                    atomicAdd(q, (unsigned long long)(long long)(int)(y00 - a0));
-                    atomicAdd(q + 1, (unsigned long long)(long long)(int)a0);
-                    atomicAdd(q + kBT, (unsigned long long)(long long)(int)(y01 - a1));
-                    atomicAdd(q + kBT + 1, (unsigned long long)(long long)(int)a1);
-                    atomicAdd(q + kBT * kBT, (unsigned long long)(long long)(int)(y10 - a2));
-                    atomicAdd(q + kBT * kBT + 1, (unsigned long long)(long long)(int)a2);
-                    atomicAdd(q + kBT * kBT + kBT, (unsigned long long)(long long)(int)(y11 - a3));
-                    atomicAdd(q + kBT * kBT + kBT + 1, (unsigned long long)(long long)(int)a3);
-                }
-                k = kend + 1;
+            if (!k_interval_coarse(r, blo, bhi, &k0, &k1)) continue;
+            long long ux = r.U[0] + (long long)k0 * r.DU[0];
+            long long uy = r.U[1] + (long long)k0 * r.DU[1];
+            long long uz = r.U[2] + (long long)k0 * r.DU[2];
+            for (int k = k0; k <= k1; ++k) {
+                const int lx = (int)(ux >> 32) - c0x, ly = (int)(uy >> 32) - c0y, lz = (int)(uz >> 32) - c0z;
+                const float wx = (float)(unsigned)ux * kInv32;
+                const float wy = (float)(unsigned)uy * kInv32;
+                const float wz = (float)(unsigned)uz * kInv32;
+                ux += r.DU[0];
+                uy += r.DU[1];
+                uz += r.DU[2];
+                if ((unsigned)lx >= (unsigned)kB || (unsigned)ly >= (unsigned)kB || (unsigned)lz >= (unsigned)kB)
+                    continue;
+                const float z1 = gr * wz, z0 = gr - z1;
+                const float y01 = z0 * wy, y00 = z0 - y01, y11 = z1 * wy, y10 = z1 - y11;
+                const float a0 = y00 * wx, a1 = y01 * wx, a2 = y10 * wx, a3 = y11 * wx;
+                unsigned long long *q = tile + (lz * kBT + ly) * kBT + lx;
+                atomicAdd(q, (unsigned long long)(long long)(int)(y00 - a0));
+                atomicAdd(q + 1, (unsigned long long)(long long)(int)a0);
+                atomicAdd(q + kBT, (unsigned long long)(long long)(int)(y01 - a1));
+                atomicAdd(q + kBT + 1, (unsigned long long)(long long)(int)a1);
+                atomicAdd(q + kBT * kBT, (unsigned long long)(long long)(int)(y10 - a2));
+                atomicAdd(q + kBT * kBT + 1, (unsigned long long)(long long)(int)a2);
+                atomicAdd(q + kBT * kBT + kBT, (unsigned long long)(long long)(int)(y11 - a3));
+                atomicAdd(q + kBT * kBT + kBT + 1, (unsigned long long)(long long)(int)a3);
             }
         }
     }
@@ -486,6 +509,7 @@ __global__ __launch_bounds__(256) void gather_bricks(const long long *__restrict
 // ---- workspace and entry points ------------------------------------------------
 struct ProjWs {
     float *vpad;
+    float *vpadT;
     float *partial;
     long long *staging;
     ushort4 *rect;
@@ -494,8 +518,8 @@ struct ProjWs {
 };
 
 int64_t ray_blocks(const dgr_geometry *G, int *tu, int *tv) {
-    *tu = (G->nu + kRayTile - 1) / kRayTile;
-    *tv = (G->nv + kRayTile - 1) / kRayTile;
+    *tu = (G->nu + kTileU - 1) / kTileU;
+    *tv = (G->nv + kTileV - 1) / kTileV;
     return (int64_t)G->n_views * (*tu) * (*tv);
 }
 
@@ -506,6 +530,7 @@ ProjWs carve_proj_ws(void *ws, const dgr_grid *grid, const dgr_geometry *geom) {
     int tu, tv;
     Carver f(ws);
     w.vpad = f.take<float>(pad_count(grid));
+    w.vpadT = f.take<float>(pad_count(grid));
     w.partial = f.take<float>(ray_blocks(geom, &tu, &tv));
     Carver b(ws);
     const Bricks bk = bricks_of(grid);
@@ -579,13 +604,15 @@ static dgr_status project_impl(const float *volume, const dgr_grid *grid, const 
     ProjWs w = carve_proj_ws(ws, grid, geom);
     PadDims p = pad_dims(grid);
     DevGrid g = dev_grid(grid);
-    pad_volume<<<dim3(grid_stride_blocks(pad_count(grid))), dim3(256), 0, st>>>(volume, g, p, w.vpad);
+    pad_volume<<<dim3(grid_stride_blocks(pad_count(grid))), dim3(256), 0, st>>>(volume, g, p, w.vpad,
+                                                                                   w.vpadT);
     DGR_LAUNCH_CHECK();
     int tu, tv;
     const int64_t nb = ray_blocks(geom, &tu, &tv);
     const double m = (double)geom->n_views * geom->nu * geom->nv;
-    project_rays<MODE><<<dim3((unsigned)nb), dim3(256), 0, st>>>(
-        w.vpad, p, g, geom_dev(geom), tu, tv, target, out, (float)(1.0 / m), w.partial);
+    const int64_t launched = (nb + kXcd - 1) / kXcd * kXcd;
+    project_rays<MODE><<<dim3((unsigned)launched), dim3(256), 0, st>>>(
+        w.vpad, w.vpadT, p, g, geom_dev(geom), tu, tv, nb, target, out, (float)(1.0 / m), w.partial);
     DGR_LAUNCH_CHECK();
     if (MODE == 1) {
         finish_loss<<<1, 256, 0, st>>>(w.partial, nb, 1.0 / m, loss);
@@ -619,12 +646,9 @@ extern "C" dgr_status dgr_backproject(const float *proj, const dgr_grid *grid,
     const int64_t nrect = bk.count() * geom->n_views;
     brick_rects<<<dim3((unsigned)((nrect + 255) / 256)), dim3(256), 0, st>>>(G, g, bk, w.rect);
     DGR_LAUNCH_CHECK();
-    // Bound on |binary32 - binary64| sample positions: offsets within a segment
-    // stay below kSeg * |du| + 1 voxel, each coordinate sees a few binary32
-    // roundings of that size; a factor 8 of margin on top.
-    const double du_max = (double)geom->step *
-                          std::max((double)grid->inv_h[0], std::max((double)grid->inv_h[1], (double)grid->inv_h[2]));
-    const float eps = (float)(8.0 * std::ldexp(kSeg * du_max + 2.0, -24) + 1e-6);
+    // Fixed-point positions differ from binary64 ones by at most
+    // (|k| + 1) * 2^-33 <= 2^-10 voxel for |k| <= 2^22; grow the brick by 2^-8.
+    const float eps = 0.00390625f;
     const int64_t nproj = (int64_t)geom->n_views * geom->nu * geom->nv;
     zero_u32<<<1, 1, 0, st>>>(w.maxbits);
     DGR_LAUNCH_CHECK();

@@ -22,11 +22,22 @@ import numpy as np
 MM_PER_UNIT = 128.0
 
 
+def _f32(x) -> float:
+    return float(np.float32(x))
+
+
 @dataclass(frozen=True)
 class GridSpec:
+    """Voxel grid.  lo and inv_h are stored rounded to binary32, the precision
+    the C ABI takes them in, so every consumer sees the same numbers."""
     dims: tuple  # (nx, ny, nz)
     lo: tuple    # world coordinate of the lower faces
     inv_h: tuple  # 1 / voxel size per axis
+
+    def __post_init__(self):
+        object.__setattr__(self, "dims", tuple(int(d) for d in self.dims))
+        object.__setattr__(self, "lo", tuple(_f32(x) for x in self.lo))
+        object.__setattr__(self, "inv_h", tuple(_f32(x) for x in self.inv_h))
 
     @property
     def shape(self):  # numpy/torch shape [nz, ny, nx]
@@ -44,12 +55,19 @@ def cube_grid(D: int) -> GridSpec:
 
 @dataclass(frozen=True)
 class Geometry:
+    """Acquisition geometry; step and length_scale are stored rounded to
+    binary32 (the ABI's precision), views are binary32."""
     kind: int          # 0 parallel, 1 cone
     views: np.ndarray  # float32 [n_views, 12]
     nu: int
     nv: int
     step: float        # march step, world units
     length_scale: float
+
+    def __post_init__(self):
+        object.__setattr__(self, "views", np.ascontiguousarray(self.views, np.float32))
+        object.__setattr__(self, "step", _f32(self.step))
+        object.__setattr__(self, "length_scale", _f32(self.length_scale))
 
     @property
     def n_views(self):

@@ -57,6 +57,11 @@ _SIGS = {
     "dgr_bbox": ("st", ["p", "p", "p", "i64", "grid", "trunc", "p", "p"]),
     "dgr_bin": ("st", ["p", "p", "p", "i64", "grid", "trunc", "p", "p", "p", "sz", "p"]),
     "dgr_check": ("st", ["p", "p"]),
+    "dgr_voxelize_f64_workspace": (ctypes.c_size_t, ["i64", "i64", "grid"]),
+    "dgr_voxelize_f64": ("st", ["p", "p", "p", "p", "i64", "grid", "trunc", "p", "p", "sz", "p"]),
+    "dgr_fd_l1_f64_workspace": (ctypes.c_size_t, ["i64", "i32", "i64", "geom"]),
+    "dgr_fd_l1_f64": ("st", ["p", "grid", "geom", "p", "p", "p", "p", "p", "i64", "trunc", "p", "p",
+                             "p", "i32", "i64", "p", "p", "sz", "p"]),
     "dgr_status_string": (ctypes.c_char_p, ["i32"]),
     "dgr_last_error": (ctypes.c_char_p, []),
     "dgr_version": (ctypes.c_int32, []),
@@ -286,3 +291,40 @@ def dgr_bin(mu, scale, quat, grid: GridSpec, k_sigma=3.0, box_half=8):
 def dgr_check(ws: Workspace):
     p, _ = ws.ptr_size(256)
     _check("dgr_check", lib().dgr_check(p, _stream()))
+
+
+def dgr_voxelize_f64(mu, scale, quat, density, grid: GridSpec, k_sigma=3.0, box_half=8,
+                     ws: Workspace | None = None):
+    n = mu.shape[0]
+    out = torch.empty(grid.shape, dtype=torch.float64, device=mu.device)
+    ws = ws or Workspace(mu.device)
+    P = dgr_voxelize_plan(mu, scale, quat, grid, k_sigma, box_half, ws)
+    g, t = c_grid(grid), c_trunc(k_sigma, box_half)
+    p, sz = ws.ptr_size(int(lib().dgr_voxelize_f64_workspace(n, P, ctypes.byref(g))))
+    _check("dgr_voxelize_f64", lib().dgr_voxelize_f64(
+        _ptr(mu), _ptr(scale), _ptr(quat), _ptr(density), n, ctypes.byref(g), ctypes.byref(t),
+        _ptr(out), p, sz, _stream()))
+    return out
+
+
+def dgr_fd_l1_f64(volume64, target, mu, scale, quat, density, grid: GridSpec, geom: Geometry,
+                  views_dev, jobs, box_cap=1 << 16, k_sigma=3.0, box_half=8):
+    """jobs: list of (gid, component, h).  Returns float64 [n_jobs, 2] of loss
+    changes (L(+h) - L, L(-h) - L), summed over views and divided by M."""
+    import numpy as np
+    n = mu.shape[0]
+    nj = len(jobs)
+    gid = np.ascontiguousarray([j[0] for j in jobs], np.int32)
+    comp = np.ascontiguousarray([j[1] for j in jobs], np.int32)
+    hh = np.ascontiguousarray([j[2] for j in jobs], np.float64)
+    out = torch.empty((nj, geom.n_views, 2), dtype=torch.float64, device=mu.device)
+    g, t, G = c_grid(grid), c_trunc(k_sigma, box_half), c_geom(geom, views_dev)
+    ws = Workspace(mu.device)
+    p, sz = ws.ptr_size(int(lib().dgr_fd_l1_f64_workspace(n, nj, int(box_cap), ctypes.byref(G))))
+    _check("dgr_fd_l1_f64", lib().dgr_fd_l1_f64(
+        _ptr(volume64), ctypes.byref(g), ctypes.byref(G), _ptr(target), _ptr(mu), _ptr(scale),
+        _ptr(quat), _ptr(density), n, ctypes.byref(t), gid.ctypes.data_as(ctypes.c_void_p),
+        comp.ctypes.data_as(ctypes.c_void_p), hh.ctypes.data_as(ctypes.c_void_p), nj, int(box_cap),
+        _ptr(out), p, sz, _stream()))
+    M = geom.n_views * geom.nu * geom.nv
+    return out.sum(dim=1) / M
