@@ -162,11 +162,52 @@ dgr_status dgr_backproject(const float *proj, const dgr_grid *grid, const dgr_ge
 
 /* ---- optimiser (sec. 5.1 Implementation Details: Adam) ------------------ */
 
-/* One Adam step in place over n entries:
+/* One Adam step in place over n entries, projected onto param >= lower:
  * m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
- * param -= lr * (m/(1-b1^step)) / (sqrt(v/(1-b2^step)) + eps);  step >= 1. */
+ * param = max(param - lr * (m/(1-b1^step)) / (sqrt(v/(1-b2^step)) + eps), lower);
+ * step >= 1; lower = -INFINITY for a plain step. */
 dgr_status dgr_adam(float *param, const float *grad, float *m, float *v, int64_t n, float lr,
-                    float b1, float b2, float eps, int64_t step, void *stream);
+                    float b1, float b2, float eps, int64_t step, float lower, void *stream);
+
+/* ---- reconstruction support: FDK, initialisation, PSNR -------------------- */
+
+/* FDK reconstruction (Feldkamp; the paper initialises Gaussian positions from
+ * an FBP/FDK volume, Fig. 4 caption, and uses FDK as a baseline, Tab. 1) of a
+ * full circular cone-beam scan on a flat detector covering `arc` radians in
+ * n_views equal steps (arc = 2*pi): cosine weighting, Ram-Lak ramp filter
+ * along detector rows (spacing |e_u| R/D at the isocentre), and voxel-driven
+ * backprojection with weight (dbeta/2)(R/U)^2, divided by length_scale.
+ * proj [n_views][nv][nu] -> volume [nz][ny][nx] (overwritten).  geom must be
+ * DGR_CONE with nu <= 16384. */
+size_t dgr_fdk_workspace(const dgr_grid *grid, const dgr_geometry *geom);
+dgr_status dgr_fdk(const float *proj, const dgr_grid *grid, const dgr_geometry *geom, float arc,
+                   float *volume, void *ws, size_t ws_bytes, void *stream);
+
+/* Bytes of workspace for dgr_psnr and dgr_fit_density_scale. */
+size_t dgr_reduce_workspace(void);
+
+/* PSNR of x against ground truth gt (App. C.1): out (DEVICE binary64 [3]) =
+ * { 10 log10(MAX^2 / MSE), MSE, MAX } with MAX = max(gt), MSE over n. */
+dgr_status dgr_psnr(const float *x, const float *gt, int64_t n, double *out, void *ws,
+                    size_t ws_bytes, void *stream);
+
+/* Initial Gaussians drawn from a volume (e.g. the FDK volume): voxels above
+ * thresh_frac * max(volume) are drawn with probability proportional to their
+ * value, with replacement; sample i takes the voxel whose cumulative-weight
+ * interval (x fastest) holds uniforms[i][0] * W, mean = voxel centre +
+ * (uniforms[i][1..3] - 1/2) voxel, isotropic scale `scale`, identity
+ * rotation, density = volume value.  uniforms [n][4] in [0, 1) (DEVICE). */
+size_t dgr_init_workspace(const dgr_grid *grid);
+dgr_status dgr_init_from_volume(const float *volume, const dgr_grid *grid, float thresh_frac,
+                                int64_t n, const float *uniforms, float scale, float *mu,
+                                float *scale_out, float *quat, float *density, void *ws,
+                                size_t ws_bytes, void *stream);
+
+/* Least-squares intensity scale: kappa = <p1, target> / <p1, p1> over m
+ * entries (binary64 sums); density[n] *= kappa; *kappa (DEVICE binary64, may
+ * be null) receives kappa. */
+dgr_status dgr_fit_density_scale(const float *p1, const float *target, int64_t m, float *density,
+                                 int64_t n, double *kappa, void *ws, size_t ws_bytes, void *stream);
 
 /* ---- binary64 path for finite-difference gradient checks ------------------ */
 
@@ -188,7 +229,7 @@ dgr_status dgr_voxelize_f64(const float *mu, const float *scale, const float *qu
  * Gaussian on its box for +h and -h.  out [n_jobs][n_views][2] (DEVICE,
  * binary64): per-view sums for +h and -h; the loss changes are their sums
  * over views divided by M = n_views*nu*nv.  job_gid, job_comp, job_h are HOST
- * arrays.  box_cap bounds the voxels of any job's box (larger boxes give 0).
+ * arrays.  box_cap bounds the voxels of any job's box (larger boxes give NaN).
  * Synchronises `stream`. */
 size_t dgr_fd_l1_f64_workspace(int64_t n, int32_t n_jobs, int64_t box_cap, const dgr_geometry *geom);
 dgr_status dgr_fd_l1_f64(const double *volume, const dgr_grid *grid, const dgr_geometry *geom,

@@ -34,6 +34,11 @@ What pins each function (tests under ``tests/test_oracle_*.py``):
   ``voxelize_box`` with frozen boxes, and by d rho = <dL/dV, G>.
 * ``l1``, ``adam``, ``psnr`` -- pinned by hand-computed values and by
   ``torch.optim.Adam`` on a special case.
+* ``fdk`` -- pinned by reconstructing a uniform ball from its analytic
+  projections (interior value and exterior zero within a few per cent), and
+  by the discrete Ram-Lak response of a single impulse.
+* ``init_from_volume`` -- pinned by brute-force inverse-CDF sampling in
+  numpy and by the sampling frequencies of a two-voxel volume.
 """
 from __future__ import annotations
 
@@ -92,6 +97,10 @@ def lib():
         L.orc_adam.restype = None
         L.orc_psnr.argtypes = [P, P, i64]
         L.orc_psnr.restype = f64
+        L.orc_fdk.argtypes = [P, i32, i32, i32, P, f64, f64, P, P, P, P]
+        L.orc_fdk.restype = None
+        L.orc_init_from_volume.argtypes = [P, P, P, P, f64, i64, P, f64, P, P, P, P, P]
+        L.orc_init_from_volume.restype = i64
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = ctypes.c_int
         _lib = L
@@ -219,6 +228,31 @@ def adam(p, g, m, v, lr, t, b1=0.9, b2=0.999, eps=1e-8):
     g = _c(g, np.float64)
     lib().orc_adam(_p(p), _p(g), _p(m), _p(v), p.size, float(lr), float(b1), float(b2),
                    float(eps), int(t))
+
+
+def fdk(proj, views, nu, nv, arc, length_scale, dims, lo, inv_h):
+    """FDK volume float64 [nz, ny, nx] from cone-beam projections."""
+    proj = _c(proj, np.float32)
+    views = _c(views, np.float32)
+    d, l, h = _grid_args(dims, lo, inv_h, np.float64)
+    V = np.zeros((dims[2], dims[1], dims[0]), np.float64)
+    lib().orc_fdk(_p(proj), views.shape[0], int(nu), int(nv), _p(views), float(arc),
+                  float(length_scale), _p(d), _p(l), _p(h), _p(V))
+    return V
+
+
+def init_from_volume(f, dims, lo, inv_h, thresh_frac, uniforms, scale):
+    """Initial Gaussians drawn from a volume; returns (mu, scale, quat, rho,
+    voxel index, count of voxels above the threshold)."""
+    f = _c(f, np.float32)
+    u = _c(uniforms, np.float64)
+    n = u.shape[0]
+    d, l, h = _grid_args(dims, lo, inv_h, np.float64)
+    mu, sc, q, rho = np.zeros((n, 3)), np.zeros((n, 3)), np.zeros((n, 4)), np.zeros(n)
+    vox = np.zeros(n, np.int64)
+    above = lib().orc_init_from_volume(_p(f), _p(d), _p(l), _p(h), float(thresh_frac), n, _p(u),
+                                       float(scale), _p(mu), _p(sc), _p(q), _p(rho), _p(vox))
+    return mu, sc, q, rho, vox, int(above)
 
 
 def psnr(x, gt):

@@ -24,6 +24,10 @@
  */
 #include <math.h>
 #include <stdint.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -642,4 +646,150 @@ int orc_num_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* O9. FDK (Feldkamp-Davis-Kress) for a full circular cone-beam scan on a   */
+/* flat detector, the textbook filtered backprojection (Kak & Slaney, the  */
+/* reference the paper cites in sec. 4.1); the paper uses an FBP/FDK        */
+/* volume to initialise Gaussian positions (Fig. 4 caption) and as a        */
+/* baseline.  Per view j (source s, detector plane with unit normal n from  */
+/* the source side, D = (det - s).n, R = -s.n):                             */
+/*  1. p_w = p * D / |pix - s|              (cosine weight)                 */
+/*  2. q = ramp filter of p_w along e_u: spacing tau = |e_u| R / D,         */
+/*     q(i) = (1/tau) [p_w(i)/4 - sum_{k odd} p_w(i-k) / (k^2 pi^2)]        */
+/*  3. f(x) += (dbeta / 2) (R / U)^2 q(a(x), b(x)), U = (x - s).n, (a, b)   */
+/*     the detector position of the ray s -> x, bilinear in q, zero outside.*/
+/* The result is divided by length_scale (projections carry that factor).   */
+/* ------------------------------------------------------------------------ */
+static void view_frame(const float *v, double s[3], double det[3], double eu[3], double ev[3],
+                       double n[3], double *D, double *R)
+{
+    for (int a = 0; a < 3; ++a) { s[a] = v[a]; det[a] = v[3 + a]; eu[a] = v[6 + a]; ev[a] = v[9 + a]; }
+    n[0] = eu[1] * ev[2] - eu[2] * ev[1];
+    n[1] = eu[2] * ev[0] - eu[0] * ev[2];
+    n[2] = eu[0] * ev[1] - eu[1] * ev[0];
+    double nn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    for (int a = 0; a < 3; ++a) n[a] /= nn;
+    double dd = (det[0] - s[0]) * n[0] + (det[1] - s[1]) * n[1] + (det[2] - s[2]) * n[2];
+    if (dd < 0) { for (int a = 0; a < 3; ++a) n[a] = -n[a]; dd = -dd; }
+    *D = dd;
+    *R = -(s[0] * n[0] + s[1] * n[1] + s[2] * n[2]);
+}
+
+void orc_fdk(const float *proj, int32_t n_views, int32_t nu, int32_t nv, const float *views,
+             double arc, double length_scale, const int32_t dims[3], const double glo[3],
+             const double inv_h[3], double *V)
+{
+    int64_t npix = (int64_t)nu * nv;
+    double *q = malloc(sizeof(double) * (size_t)(n_views * npix));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t jr = 0; jr < (int64_t)n_views * nv; ++jr) {
+        int64_t j = jr / nv, iv = jr % nv;
+        double s[3], det[3], eu[3], ev[3], n[3], D, R;
+        view_frame(views + 12 * j, s, det, eu, ev, n, &D, &R);
+        double pu = sqrt(eu[0] * eu[0] + eu[1] * eu[1] + eu[2] * eu[2]);
+        double tau = pu * R / D;
+        double *row = malloc(sizeof(double) * (size_t)nu);
+        for (int64_t iu = 0; iu < nu; ++iu) {
+            double au = (double)iu - 0.5 * (nu - 1), av = (double)iv - 0.5 * (nv - 1), r2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                double d = det[a] + au * eu[a] + av * ev[a] - s[a];
+                r2 += d * d;
+            }
+            row[iu] = (double)proj[(j * nv + iv) * nu + iu] * D / sqrt(r2);
+        }
+        for (int64_t i = 0; i < nu; ++i) {
+            double acc = 0.25 * row[i];
+            for (int64_t k = 1; k < nu; k += 2) {
+                double w = 1.0 / ((double)k * (double)k * M_PI * M_PI);
+                if (i - k >= 0) acc -= w * row[i - k];
+                if (i + k < nu) acc -= w * row[i + k];
+            }
+            q[(j * nv + iv) * nu + i] = acc / tau;
+        }
+        free(row);
+    }
+    double dbeta = arc / (double)n_views;
+    int64_t nx = dims[0], ny = dims[1], nz = dims[2];
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t jj = 0; jj < ny; ++jj)
+            for (int64_t i = 0; i < nx; ++i) {
+                double x[3] = {glo[0] + (i + 0.5) / inv_h[0], glo[1] + (jj + 0.5) / inv_h[1],
+                               glo[2] + (k + 0.5) / inv_h[2]};
+                double acc = 0.0;
+                for (int64_t j = 0; j < n_views; ++j) {
+                    double s[3], det[3], eu[3], ev[3], n[3], D, R;
+                    view_frame(views + 12 * j, s, det, eu, ev, n, &D, &R);
+                    double r[3] = {x[0] - s[0], x[1] - s[1], x[2] - s[2]};
+                    double U = r[0] * n[0] + r[1] * n[1] + r[2] * n[2];
+                    if (!(U > 0)) continue;
+                    double hit[3];
+                    for (int a = 0; a < 3; ++a) hit[a] = s[a] + (D / U) * r[a] - det[a];
+                    double uu = eu[0] * eu[0] + eu[1] * eu[1] + eu[2] * eu[2];
+                    double vv = ev[0] * ev[0] + ev[1] * ev[1] + ev[2] * ev[2];
+                    double a_pix = (hit[0] * eu[0] + hit[1] * eu[1] + hit[2] * eu[2]) / uu + 0.5 * (nu - 1);
+                    double b_pix = (hit[0] * ev[0] + hit[1] * ev[1] + hit[2] * ev[2]) / vv + 0.5 * (nv - 1);
+                    double fa = floor(a_pix), fb = floor(b_pix), wa = a_pix - fa, wb = b_pix - fb;
+                    double val = 0.0;
+                    for (int c = 0; c < 4; ++c) {
+                        int64_t ia = (int64_t)fa + (c & 1), ib = (int64_t)fb + (c >> 1);
+                        if (ia < 0 || ib < 0 || ia >= nu || ib >= nv) continue;
+                        double w = ((c & 1) ? wa : 1 - wa) * ((c >> 1) ? wb : 1 - wb);
+                        val += w * q[(j * nv + ib) * nu + ia];
+                    }
+                    acc += (R / U) * (R / U) * val;
+                }
+                V[(k * ny + jj) * nx + i] = 0.5 * dbeta * acc / length_scale;
+            }
+    free(q);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Initial Gaussians drawn from a volume (the paper places the initial      */
+/* Gaussians from an FBP volume, Fig. 4 caption).  Voxels above             */
+/* thresh_frac * max(f) are drawn with probability proportional to f, with  */
+/* replacement: sample i takes the first voxel v (x fastest) whose          */
+/* cumulative weight exceeds u_i0 * W.  Its mean is the voxel centre plus   */
+/* (u_i1..3 - 1/2) voxel, isotropic scale `scale`, identity rotation and    */
+/* density f(v).  uniforms [n][4] in [0, 1).  Returns the number of voxels  */
+/* above the threshold.                                                     */
+/* ------------------------------------------------------------------------ */
+int64_t orc_init_from_volume(const float *f, const int32_t dims[3], const double glo[3],
+                             const double inv_h[3], double thresh_frac, int64_t n,
+                             const double *uniforms, double scale, double *mu, double *sc,
+                             double *quat, double *rho, int64_t *voxel)
+{
+    int64_t nvox = (int64_t)dims[0] * dims[1] * dims[2];
+    double mx = -INFINITY;
+    for (int64_t v = 0; v < nvox; ++v) if (f[v] > mx) mx = f[v];
+    double tau = thresh_frac * mx;
+    double *cdf = malloc(sizeof(double) * (size_t)nvox);
+    double run = 0.0;
+    int64_t above = 0;
+    for (int64_t v = 0; v < nvox; ++v) {
+        if ((double)f[v] > tau) { run += (double)f[v]; ++above; }
+        cdf[v] = run;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        double target = uniforms[4 * i] * run;
+        int64_t lo = 0, hi = nvox - 1;  /* first v with cdf[v] > target */
+        while (lo < hi) {
+            int64_t mid = (lo + hi) / 2;
+            if (cdf[mid] > target) hi = mid; else lo = mid + 1;
+        }
+        int64_t v = lo;
+        voxel[i] = v;
+        int64_t x = v % dims[0], y = (v / dims[0]) % dims[1], z = v / ((int64_t)dims[0] * dims[1]);
+        int64_t idx[3] = {x, y, z};
+        for (int a = 0; a < 3; ++a) {
+            mu[3 * i + a] = glo[a] + (idx[a] + 0.5 + (uniforms[4 * i + 1 + a] - 0.5)) / inv_h[a];
+            sc[3 * i + a] = scale;
+        }
+        quat[4 * i] = 1.0; quat[4 * i + 1] = quat[4 * i + 2] = quat[4 * i + 3] = 0.0;
+        rho[i] = (double)f[v];
+    }
+    free(cdf);
+    return above;
 }

@@ -66,9 +66,9 @@ __global__ __launch_bounds__(kThreads) void scan_reduce(const Tin *__restrict__ 
 
 // Single block: exclusive scan of the block sums in place; the grand total
 // goes to *total (may be null).
-template <class Tout>
+template <class Tout, class Ttot>
 __global__ __launch_bounds__(kThreads) void scan_top(Tout *__restrict__ blk, int64_t nb,
-                                                     uint64_t *__restrict__ total) {
+                                                     Ttot *__restrict__ total) {
     Tout carry = 0;
     for (int64_t c = 0; c < nb; c += kThreads) {
         int64_t j = c + threadIdx.x;
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(kThreads) void scan_top(Tout *__restrict__ blk, int
         if (j < nb) blk[j] = carry + ex;
         carry += tot;
     }
-    if (threadIdx.x == 0 && total) *total = (uint64_t)carry;
+    if (threadIdx.x == 0 && total) *total = (Ttot)carry;
 }
 
 template <class Tin, class Tout>
@@ -104,13 +104,13 @@ __global__ __launch_bounds__(kThreads) void scan_apply(const Tin *__restrict__ i
     }
 }
 
-template <class Tin, class Tout>
-dgr_status exclusive_scan(const Tin *in, Tout *out, int64_t n, Tout *blk, uint64_t *total,
+template <class Tin, class Tout, class Ttot>
+dgr_status exclusive_scan(const Tin *in, Tout *out, int64_t n, Tout *blk, Ttot *total,
                           hipStream_t st) {
     int64_t nb = std::max<int64_t>(1, (n + kTile - 1) / kTile);
     scan_reduce<Tin, Tout><<<dim3((unsigned)nb), dim3(kThreads), 0, st>>>(in, n, blk);
     DGR_LAUNCH_CHECK();
-    scan_top<Tout><<<dim3(1), dim3(kThreads), 0, st>>>(blk, nb, total);
+    scan_top<Tout, Ttot><<<dim3(1), dim3(kThreads), 0, st>>>(blk, nb, total);
     DGR_LAUNCH_CHECK();
     scan_apply<Tin, Tout><<<dim3((unsigned)nb), dim3(kThreads), 0, st>>>(in, n, blk, out);
     DGR_LAUNCH_CHECK();
@@ -236,6 +236,13 @@ int key_bits(int64_t T) {
 
 }  // namespace
 
+int64_t scan_f64_blocks(int64_t n) { return std::max<int64_t>(1, (n + kTile - 1) / kTile) + 1; }
+
+dgr_status exclusive_scan_f64(const float *in, double *out, int64_t n, double *blk, double *total,
+                              hipStream_t st) {
+    return exclusive_scan<float, double, double>(in, out, n, blk, total, st);
+}
+
 VoxWs carve_vox_ws(void *ws, int64_t n, int64_t cap, const dgr_grid *grid) {
     VoxWs w{};
     Carver c(ws);
@@ -283,7 +290,7 @@ dgr_status enqueue_count_only(const float *mu, const float *scale, const float *
     zero_total<<<1, 1, 0, st>>>(w.hdr);
     DGR_LAUNCH_CHECK();
     if (n == 0) return DGR_OK;
-    return exclusive_scan<uint32_t, uint64_t>(w.count, w.offset, n, w.scan_blk, &w.hdr->total, st);
+    return exclusive_scan<uint32_t, uint64_t, uint64_t>(w.count, w.offset, n, w.scan_blk, &w.hdr->total, st);
 }
 
 dgr_status enqueue_binning(const float *mu, const float *scale, const float *quat,
@@ -295,7 +302,7 @@ dgr_status enqueue_binning(const float *mu, const float *scale, const float *qua
     if (n > 0) {
         s = launch_prep(mu, scale, quat, density, n, grid, trunc, w.rec, w.count, nullptr, st);
         if (s != DGR_OK) return s;
-        s = exclusive_scan<uint32_t, uint64_t>(w.count, w.offset, n, w.scan_blk, &w.hdr->total, st);
+        s = exclusive_scan<uint32_t, uint64_t, uint64_t>(w.count, w.offset, n, w.scan_blk, &w.hdr->total, st);
         if (s != DGR_OK) return s;
         const int Tx = (grid->dims[0] + 7) / 8, Ty = (grid->dims[1] + 7) / 8;
         emit_pairs<<<dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, st>>>(
@@ -308,8 +315,9 @@ dgr_status enqueue_binning(const float *mu, const float *scale, const float *qua
         radix_hist<<<dim3(w.radix_blocks), dim3(kThreads), 0, st>>>(w.key[cur], w.hdr, w.cap,
                                                                    w.radix_blocks, shift, w.hist);
         DGR_LAUNCH_CHECK();
-        s = exclusive_scan<uint32_t, uint32_t>(w.hist, w.hist, (int64_t)256 * w.radix_blocks,
-                                               reinterpret_cast<uint32_t *>(w.scan_blk), nullptr, st);
+        s = exclusive_scan<uint32_t, uint32_t, uint32_t>(w.hist, w.hist, (int64_t)256 * w.radix_blocks,
+                                                         reinterpret_cast<uint32_t *>(w.scan_blk),
+                                                         (uint32_t *)nullptr, st);
         if (s != DGR_OK) return s;
         radix_scatter<<<dim3(w.radix_blocks), dim3(kThreads), 0, st>>>(
             w.key[cur], w.val[cur], w.key[cur ^ 1], w.val[cur ^ 1], w.hdr, w.cap, w.radix_blocks,

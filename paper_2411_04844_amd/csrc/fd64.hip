@@ -241,7 +241,9 @@ __global__ __launch_bounds__(256) void fd_rays(const double *__restrict__ V, Dev
     const int32_t *b = box + 6 * (int64_t)J.gid;
     const int n3b[3] = {b[3] - b[0] + 1, b[4] - b[1] + 1, b[5] - b[2] + 1};
     double sp = 0.0, sm = 0.0;
-    if (n3b[0] > 0 && n3b[1] > 0 && n3b[2] > 0 && (int64_t)n3b[0] * n3b[1] * n3b[2] <= box_cap) {
+    const bool nonempty = n3b[0] > 0 && n3b[1] > 0 && n3b[2] > 0;
+    const bool too_big = nonempty && (int64_t)n3b[0] * n3b[1] * n3b[2] > box_cap;
+    if (nonempty && !too_big) {
         const int o3b[3] = {b[0], b[1], b[2]};
         const int n3v[3] = {g.nx, g.ny, g.nz};
         const int o3v[3] = {0, 0, 0};
@@ -287,6 +289,7 @@ __global__ __launch_bounds__(256) void fd_rays(const double *__restrict__ V, Dev
     }
     sp = block_sum(sp, sh);
     sm = block_sum(sm, sh);
+    if (too_big) sp = sm = __builtin_nan("");  // a box larger than box_cap is reported, not skipped
     if (threadIdx.x == 0) {
         out[((int64_t)jb * G.n_views + j) * 2 + 0] = sp;
         out[((int64_t)jb * G.n_views + j) * 2 + 1] = sm;

@@ -185,6 +185,12 @@ dgr_status enqueue_count_only(const float *mu, const float *scale, const float *
                               const dgr_grid *grid, const dgr_trunc *trunc, VoxWs &w,
                               hipStream_t st);
 
+// Exclusive prefix sum of binary32 values in binary64; *total gets the sum.
+// blk needs scan_f64_blocks(n) entries.
+int64_t scan_f64_blocks(int64_t n);
+dgr_status exclusive_scan_f64(const float *in, double *out, int64_t n, double *blk, double *total,
+                              hipStream_t st);
+
 inline int64_t tiles_of(const dgr_grid *g) {
     return (int64_t)((g->dims[0] + 7) / 8) * ((g->dims[1] + 7) / 8) * ((g->dims[2] + 7) / 8);
 }

@@ -53,7 +53,7 @@ _SIGS = {
     "dgr_project": ("st", ["p", "grid", "geom", "p", "p", "sz", "p"]),
     "dgr_project_l1": ("st", ["p", "grid", "geom", "p", "p", "p", "p", "sz", "p"]),
     "dgr_backproject": ("st", ["p", "grid", "geom", "p", "p", "sz", "p"]),
-    "dgr_adam": ("st", ["p", "p", "p", "p", "i64", "f32", "f32", "f32", "f32", "i64", "p"]),
+    "dgr_adam": ("st", ["p", "p", "p", "p", "i64", "f32", "f32", "f32", "f32", "i64", "f32", "p"]),
     "dgr_bbox": ("st", ["p", "p", "p", "i64", "grid", "trunc", "p", "p"]),
     "dgr_bin": ("st", ["p", "p", "p", "i64", "grid", "trunc", "p", "p", "p", "sz", "p"]),
     "dgr_check": ("st", ["p", "p"]),
@@ -62,6 +62,14 @@ _SIGS = {
     "dgr_fd_l1_f64_workspace": (ctypes.c_size_t, ["i64", "i32", "i64", "geom"]),
     "dgr_fd_l1_f64": ("st", ["p", "grid", "geom", "p", "p", "p", "p", "p", "i64", "trunc", "p", "p",
                              "p", "i32", "i64", "p", "p", "sz", "p"]),
+    "dgr_fdk_workspace": (ctypes.c_size_t, ["grid", "geom"]),
+    "dgr_fdk": ("st", ["p", "grid", "geom", "f32", "p", "p", "sz", "p"]),
+    "dgr_reduce_workspace": (ctypes.c_size_t, []),
+    "dgr_psnr": ("st", ["p", "p", "i64", "p", "p", "sz", "p"]),
+    "dgr_init_workspace": (ctypes.c_size_t, ["grid"]),
+    "dgr_init_from_volume": ("st", ["p", "grid", "f32", "i64", "p", "f32", "p", "p", "p", "p", "p",
+                                    "sz", "p"]),
+    "dgr_fit_density_scale": ("st", ["p", "p", "i64", "p", "i64", "p", "p", "sz", "p"]),
     "dgr_status_string": (ctypes.c_char_p, ["i32"]),
     "dgr_last_error": (ctypes.c_char_p, []),
     "dgr_version": (ctypes.c_int32, []),
@@ -255,12 +263,12 @@ def dgr_backproject(proj, grid: GridSpec, geom: Geometry, views_dev, out=None,
     return out
 
 
-def dgr_adam(param, grad, m, v, lr, step, b1=0.9, b2=0.999, eps=1e-8):
+def dgr_adam(param, grad, m, v, lr, step, b1=0.9, b2=0.999, eps=1e-8, lower=float("-inf")):
     for name, t in (("param", param), ("grad", grad), ("m", m), ("v", v)):
         _need(t, torch.float32, param.shape, name)
     _check("dgr_adam", lib().dgr_adam(_ptr(param), _ptr(grad), _ptr(m), _ptr(v), param.numel(),
                                        float(lr), float(b1), float(b2), float(eps), int(step),
-                                       _stream()))
+                                       float(lower), _stream()))
 
 
 def dgr_bbox(mu, scale, quat, grid: GridSpec, k_sigma=3.0, box_half=8):
@@ -328,3 +336,59 @@ def dgr_fd_l1_f64(volume64, target, mu, scale, quat, density, grid: GridSpec, ge
         _ptr(out), p, sz, _stream()))
     M = geom.n_views * geom.nu * geom.nv
     return out.sum(dim=1) / M
+
+
+def dgr_fdk(proj, grid: GridSpec, geom: Geometry, views_dev, arc=2 * 3.141592653589793, out=None,
+            ws: Workspace | None = None):
+    _need(proj, torch.float32, (geom.n_views, geom.nv, geom.nu), "proj")
+    if out is None:
+        out = torch.empty(grid.shape, dtype=torch.float32, device=proj.device)
+    g, G = c_grid(grid), c_geom(geom, views_dev)
+    ws = ws or Workspace(proj.device)
+    p, sz = ws.ptr_size(int(lib().dgr_fdk_workspace(ctypes.byref(g), ctypes.byref(G))))
+    _check("dgr_fdk", lib().dgr_fdk(_ptr(proj), ctypes.byref(g), ctypes.byref(G), float(arc),
+                                    _ptr(out), p, sz, _stream()))
+    return out
+
+
+def dgr_psnr(x, gt, out=None, ws: Workspace | None = None):
+    """Device tensor float64 [3] = (psnr, mse, max)."""
+    _need(x, torch.float32, None, "x")
+    _need(gt, torch.float32, tuple(x.shape), "gt")
+    if out is None:
+        out = torch.empty(3, dtype=torch.float64, device=x.device)
+    ws = ws or Workspace(x.device)
+    p, sz = ws.ptr_size(int(lib().dgr_reduce_workspace()))
+    _check("dgr_psnr", lib().dgr_psnr(_ptr(x), _ptr(gt), x.numel(), _ptr(out), p, sz, _stream()))
+    return out
+
+
+def dgr_init_from_volume(volume, grid: GridSpec, n, uniforms, scale, thresh_frac=0.1,
+                         ws: Workspace | None = None):
+    _need(volume, torch.float32, grid.shape, "volume")
+    _need(uniforms, torch.float32, (n, 4), "uniforms")
+    dev = volume.device
+    mu = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    sc = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    q = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    rho = torch.empty(n, dtype=torch.float32, device=dev)
+    g = c_grid(grid)
+    ws = ws or Workspace(dev)
+    p, sz = ws.ptr_size(int(lib().dgr_init_workspace(ctypes.byref(g))))
+    _check("dgr_init_from_volume", lib().dgr_init_from_volume(
+        _ptr(volume), ctypes.byref(g), float(thresh_frac), int(n), _ptr(uniforms), float(scale),
+        _ptr(mu), _ptr(sc), _ptr(q), _ptr(rho), p, sz, _stream()))
+    return mu, sc, q, rho
+
+
+def dgr_fit_density_scale(p1, target, density, kappa=None, ws: Workspace | None = None):
+    _need(p1, torch.float32, None, "p1")
+    _need(target, torch.float32, tuple(p1.shape), "target")
+    ws = ws or Workspace(p1.device)
+    if kappa is None:
+        kappa = torch.empty(1, dtype=torch.float64, device=p1.device)
+    p, sz = ws.ptr_size(int(lib().dgr_reduce_workspace()))
+    _check("dgr_fit_density_scale", lib().dgr_fit_density_scale(
+        _ptr(p1), _ptr(target), p1.numel(), _ptr(density), density.numel(), _ptr(kappa), p, sz,
+        _stream()))
+    return kappa

@@ -61,6 +61,9 @@ class Iteration:
         self.m = {k: torch.zeros_like(P[k]) for k in self.ORDER}
         self.v = {k: torch.zeros_like(P[k]) for k in self.ORDER}
         self.t = 0
+        # projected steps: scales stay above 1/20 voxel, densities non-negative
+        h = 1.0 / max(prob.grid.inv_h)
+        self.lower = {"mu": float("-inf"), "scale": 0.05 * h, "quat": float("-inf"), "density": 0.0}
         # allocate the workspaces once, outside any timed region
         self.vox_ws.get(native.dgr_voxelize_workspace(P["mu"].shape[0], self.max_pairs, prob.grid))
         self.proj_ws.get(native.dgr_project_workspace(prob.grid, prob.geom, prob.views))
@@ -90,7 +93,7 @@ class Iteration:
         self.t += 1
         for k in self.ORDER:
             native.dgr_adam(self.p.params[k], self.grads[k], self.m[k], self.v[k],
-                            getattr(self.p.lr, k), self.t)
+                            getattr(self.p.lr, k), self.t, lower=self.lower[k])
 
     STAGES = ("voxelize", "project_l1", "backproject", "voxelize_backward", "adam")
 
@@ -112,6 +115,17 @@ class Iteration:
         """Raise if a voxelization overflowed its pair capacity."""
         native.dgr_check(self.vox_ws)
 
+    def replan(self, headroom: float = 1.25):
+        """Synchronising: grow the pair capacity if the boxes now need more."""
+        P, pr = self.p.params, self.p
+        pairs = native.dgr_voxelize_plan(P["mu"], P["scale"], P["quat"], pr.grid, pr.k_sigma,
+                                         pr.box_half, self.vox_ws)
+        if pairs * headroom > self.max_pairs:
+            self.max_pairs = int(pairs * 1.5) + 1024
+            self.vox_ws.get(native.dgr_voxelize_workspace(P["mu"].shape[0], self.max_pairs,
+                                                          pr.grid))
+        return pairs
+
 
 # --------------------------------------------------------------------------
 # workload builders
@@ -129,3 +143,79 @@ def cone_problem(D=256, n=100_000, n_views=360, n_det=512, pitch_mm=0.8, s_lo=0.
     params = {k: torch.as_tensor(G[k]).to(device).contiguous() for k in Iteration.ORDER}
     views = torch.as_tensor(geom.views).to(device).contiguous()
     return Problem(grid, geom, views, y, params)
+
+
+# --------------------------------------------------------------------------
+# sparse-view reconstruction loop
+# --------------------------------------------------------------------------
+def sparse_view_problem(D=256, n_views=25, n_det=512, pitch_mm=0.8, seeds=(3002, 3003),
+                        device="cuda"):
+    """Cone-beam sparse-view workload and its ground-truth volume (the phantom
+    averaged over 4^3 points per voxel).  Parameters are filled in by an
+    initialisation."""
+    grid = inputs.cube_grid(D)
+    geom = inputs.cone_workload(D, n_views, n_det, pitch_mm)
+    ph = inputs.ellipsoid_phantom(seeds[0])
+    y = inputs.add_noise(inputs.phantom_projections(ph, geom, device=device), seeds[1]).contiguous()
+    gt = inputs.phantom_volume(ph, grid, device=device).to(torch.float32).contiguous()
+    views = torch.as_tensor(geom.views).to(device).contiguous()
+    return Problem(grid, geom, views, y, {}), gt
+
+
+def fdk_init(prob: Problem, n=50_000, seed=3004, scale_vox=1.5, thresh=0.1):
+    """FDK volume -> n Gaussians drawn where it exceeds thresh * max, isotropic
+    scale of scale_vox voxels, density = FDK value times the least-squares
+    scale that best fits the projections.  Returns the parameter dict."""
+    dev = prob.target.device
+    f = native.dgr_fdk(prob.target, prob.grid, prob.geom, prob.views)
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    uni = torch.rand((n, 4), generator=g, dtype=torch.float32).to(dev)
+    h = 1.0 / prob.grid.inv_h[0]
+    mu, sc, q, rho = native.dgr_init_from_volume(f, prob.grid, n, uni, scale_vox * h, thresh)
+    V1 = native.dgr_voxelize(mu, sc, q, rho, prob.grid, prob.k_sigma, prob.box_half)
+    P1 = native.dgr_project(V1, prob.grid, prob.geom, prob.views)
+    native.dgr_fit_density_scale(P1, prob.target, rho)
+    return {"mu": mu, "scale": sc, "quat": q, "density": rho}
+
+
+def random_init(prob: Problem, n=50_000, seed=3005, s_lo=0.004, s_hi=0.03):
+    """Random Gaussians (the fallback initialisation), densities fitted to the
+    projections by the same least-squares scale."""
+    dev = prob.target.device
+    G = inputs.gaussians(n, seed, s_lo, s_hi)
+    P = {k: torch.as_tensor(G[k]).to(dev).contiguous() for k in Iteration.ORDER}
+    V1 = native.dgr_voxelize(P["mu"], P["scale"], P["quat"], P["density"], prob.grid,
+                             prob.k_sigma, prob.box_half)
+    P1 = native.dgr_project(V1, prob.grid, prob.geom, prob.views)
+    native.dgr_fit_density_scale(P1, prob.target, P["density"])
+    return P
+
+
+def reconstruct(prob: Problem, gt, max_iters=5000, target_psnr=35.0, check_every=10, log=None,
+                t_start=None):
+    """Run fwd+bwd+Adam iterations until the volume PSNR against gt reaches
+    target_psnr (checked every check_every iterations) or max_iters.  Returns
+    a dict with the iteration count, seconds since t_start and the history."""
+    import time
+    t0 = time.perf_counter() if t_start is None else t_start
+    it = Iteration(prob)
+    psnr_out = torch.empty(3, dtype=torch.float64, device=prob.target.device)
+    hist = []
+    reached = None
+    for i in range(1, max_iters + 1):
+        it.step()
+        if i % check_every == 0 or i == max_iters:
+            it.voxelize()
+            native.dgr_psnr(it.V, gt, out=psnr_out)
+            val = float(psnr_out[0])  # synchronises
+            it.check()
+            it.replan()
+            hist.append((i, time.perf_counter() - t0, val, float(it.loss)))
+            if log:
+                log(f"iter {i}: PSNR {val:.2f} dB, loss {float(it.loss):.5g}, "
+                    f"{time.perf_counter() - t0:.1f}s")
+            if val >= target_psnr:
+                reached = i
+                break
+    return {"iterations": reached, "seconds": (time.perf_counter() - t0) if reached else None,
+            "final_psnr": hist[-1][2] if hist else None, "history": hist}

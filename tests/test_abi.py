@@ -75,8 +75,9 @@ def test_host_validation_returns_status_without_launch():
     assert L.dgr_project(fake, ctypes.byref(g), ctypes.byref(geom), fake, fake, 1 << 30, None) == 1
     assert b"step" in L.dgr_last_error()
     # Adam hyper-parameters
-    assert L.dgr_adam(fake, fake, fake, fake, 10, 1e-3, 0.9, 0.999, 1e-8, 0, None) == 1
-    assert L.dgr_adam(fake, fake, fake, fake, 10, 1e-3, 1.5, 0.999, 1e-8, 1, None) == 1
+    assert L.dgr_adam(fake, fake, fake, fake, 10, 1e-3, 0.9, 0.999, 1e-8, 0, -1.0, None) == 1
+    assert L.dgr_adam(fake, fake, fake, fake, 10, 1e-3, 1.5, 0.999, 1e-8, 1, -1.0, None) == 1
+    assert L.dgr_adam(fake, fake, fake, fake, 10, 1e-3, 0.9, 0.999, 1e-8, 1, float("nan"), None) == 1
     # negative n
     assert L.dgr_bbox(fake, fake, fake, -1, ctypes.byref(g), ctypes.byref(t), fake, None) == 1
     # n == 0 is a no-op that succeeds without touching the device
