@@ -178,7 +178,8 @@ dgr_status dgr_adam(float *param, const float *grad, float *m, float *v, int64_t
  * along detector rows (spacing |e_u| R/D at the isocentre), and voxel-driven
  * backprojection with weight (dbeta/2)(R/U)^2, divided by length_scale.
  * proj [n_views][nv][nu] -> volume [nz][ny][nx] (overwritten).  geom must be
- * DGR_CONE with nu <= 16384. */
+ * DGR_CONE with nu <= 8192 (a filtered row is staged in LDS in binary64).
+ * Returns DGR_ERR_INVALID_ARG otherwise; all pointers are DEVICE pointers. */
 size_t dgr_fdk_workspace(const dgr_grid *grid, const dgr_geometry *geom);
 dgr_status dgr_fdk(const float *proj, const dgr_grid *grid, const dgr_geometry *geom, float arc,
                    float *volume, void *ws, size_t ws_bytes, void *stream);

@@ -57,10 +57,12 @@ __global__ void fdk_frames(const float *__restrict__ views, int n_views, FdkView
 
 // One work-group per (detector row, view): cosine weight, then the discrete
 // Ram-Lak filter q(i) = (1/tau) [p(i)/4 - sum_{k odd} (p(i-k) + p(i+k)) / (k^2 pi^2)].
+// The row and the sum are kept in binary64: the taps cancel strongly inside
+// a uniform object.  Only q is rounded to binary32.
 __global__ __launch_bounds__(256) void fdk_filter(const float *__restrict__ proj, const float *__restrict__ views,
                                                   const FdkView *__restrict__ frames, int nu, int nv,
                                                   float *__restrict__ q) {
-    extern __shared__ float row[];
+    extern __shared__ double row[];
     const int iv = blockIdx.x, j = blockIdx.y;
     const FdkView &f = frames[j];
     const float *v = views + 12 * (int64_t)j;
@@ -73,21 +75,19 @@ __global__ __launch_bounds__(256) void fdk_filter(const float *__restrict__ proj
             const double d = (double)v[3 + a] + au * (double)v[6 + a] + av * (double)v[9 + a] - f.s[a];
             r2 += d * d;
         }
-        row[i] = (float)((double)src[i] * f.D / sqrt(r2));
+        row[i] = (double)src[i] * f.D / sqrt(r2);
     }
     __syncthreads();
-    const float c = (float)(1.0 / (kPi * kPi));
-    const float inv_tau = (float)(1.0 / f.tau);
+    const double c = 1.0 / (kPi * kPi);
     float *dst = q + ((int64_t)j * nv + iv) * nu;
     for (int i = threadIdx.x; i < nu; i += 256) {
-        float acc = 0.0f;
+        double acc = 0.0;
         for (int k = 1; k < nu; k += 2) {
-            const float w = c / ((float)k * (float)k);
-            const float l = i - k >= 0 ? row[i - k] : 0.0f;
-            const float r = i + k < nu ? row[i + k] : 0.0f;
-            acc = fmaf(w, l + r, acc);
+            const double l = i - k >= 0 ? row[i - k] : 0.0;
+            const double r = i + k < nu ? row[i + k] : 0.0;
+            acc += (c / ((double)k * (double)k)) * (l + r);
         }
-        dst[i] = (0.25f * row[i] - acc) * inv_tau;
+        dst[i] = (float)((0.25 * row[i] - acc) / f.tau);
     }
 }
 
@@ -116,9 +116,10 @@ __global__ __launch_bounds__(256) void fdk_backproject(const float *__restrict__
             const double ap = hit[0] * f.eu_n[0] + hit[1] * f.eu_n[1] + hit[2] * f.eu_n[2] + 0.5 * (nu - 1);
             const double bp = hit[0] * f.ev_n[0] + hit[1] * f.ev_n[1] + hit[2] * f.ev_n[2] + 0.5 * (nv - 1);
             const double fa = floor(ap), fb = floor(bp);
-            if (fa < -1.0 || fb < -1.0 || fa > (double)nu || fb > (double)nv) continue;
+            // both taps of an axis outside the detector: nothing to add
+            if (!(fa >= -1.0 && fb >= -1.0 && fa <= (double)(nu - 1) && fb <= (double)(nv - 1))) continue;
             const float wa = (float)(ap - fa), wb = (float)(bp - fb);
-            const int ia = (int)fa, ib = (int)fb;
+            const int ia = (int)fa, ib = (int)fb;  // in [-1, nu - 1] x [-1, nv - 1]
             const float *qj = q + (int64_t)j * nv * nu;
             const bool a0 = ia >= 0, a1 = ia + 1 < nu, b0 = ib >= 0, b1 = ib + 1 < nv;
             const float q00 = (a0 && b0) ? qj[(int64_t)ib * nu + ia] : 0.0f;
@@ -289,7 +290,7 @@ dgr_status check_cone(const dgr_geometry *geom) {
     dgr_status s = check_geometry(geom);
     if (s != DGR_OK) return s;
     DGR_CHECK(geom->kind == DGR_CONE, "FDK needs a cone-beam geometry");
-    DGR_CHECK(geom->nu <= 16384, "FDK rows are staged in LDS: nu <= 16384");
+    DGR_CHECK(geom->nu <= 8192, "FDK rows are staged in LDS as binary64: nu <= 8192");
     return DGR_OK;
 }
 
@@ -320,7 +321,7 @@ extern "C" dgr_status dgr_fdk(const float *proj, const dgr_grid *grid, const dgr
     float *q = c.take<float>((int64_t)geom->n_views * geom->nu * geom->nv);
     fdk_frames<<<dim3((geom->n_views + 63) / 64), dim3(64), 0, st>>>(geom->views, geom->n_views, frames);
     DGR_LAUNCH_CHECK();
-    fdk_filter<<<dim3(geom->nv, geom->n_views), dim3(256), sizeof(float) * geom->nu, st>>>(
+    fdk_filter<<<dim3(geom->nv, geom->n_views), dim3(256), sizeof(double) * geom->nu, st>>>(
         proj, geom->views, frames, geom->nu, geom->nv, q);
     DGR_LAUNCH_CHECK();
     const int64_t nvox = (int64_t)grid->dims[0] * grid->dims[1] * grid->dims[2];

@@ -61,6 +61,7 @@ class Iteration:
         self.m = {k: torch.zeros_like(P[k]) for k in self.ORDER}
         self.v = {k: torch.zeros_like(P[k]) for k in self.ORDER}
         self.t = 0
+        self.lr_factor = 1.0  # multiplies every group's rate (schedules)
         # projected steps: scales stay above 1/20 voxel, densities non-negative
         h = 1.0 / max(prob.grid.inv_h)
         self.lower = {"mu": float("-inf"), "scale": 0.05 * h, "quat": float("-inf"), "density": 0.0}
@@ -93,7 +94,7 @@ class Iteration:
         self.t += 1
         for k in self.ORDER:
             native.dgr_adam(self.p.params[k], self.grads[k], self.m[k], self.v[k],
-                            getattr(self.p.lr, k), self.t, lower=self.lower[k])
+                            getattr(self.p.lr, k) * self.lr_factor, self.t, lower=self.lower[k])
 
     STAGES = ("voxelize", "project_l1", "backproject", "voxelize_backward", "adam")
 
@@ -149,14 +150,15 @@ def cone_problem(D=256, n=100_000, n_views=360, n_det=512, pitch_mm=0.8, s_lo=0.
 # sparse-view reconstruction loop
 # --------------------------------------------------------------------------
 def sparse_view_problem(D=256, n_views=25, n_det=512, pitch_mm=0.8, seeds=(3002, 3003),
-                        device="cuda"):
+                        device="cuda", noise_frac=0.01):
     """Cone-beam sparse-view workload and its ground-truth volume (the phantom
-    averaged over 4^3 points per voxel).  Parameters are filled in by an
-    initialisation."""
+    averaged over 4^3 points per voxel); the target carries Gaussian noise of
+    noise_frac * max(y).  Parameters are filled in by an initialisation."""
     grid = inputs.cube_grid(D)
     geom = inputs.cone_workload(D, n_views, n_det, pitch_mm)
     ph = inputs.ellipsoid_phantom(seeds[0])
-    y = inputs.add_noise(inputs.phantom_projections(ph, geom, device=device), seeds[1]).contiguous()
+    y = inputs.add_noise(inputs.phantom_projections(ph, geom, device=device), seeds[1],
+                         noise_frac).contiguous()
     gt = inputs.phantom_volume(ph, grid, device=device).to(torch.float32).contiguous()
     views = torch.as_tensor(geom.views).to(device).contiguous()
     return Problem(grid, geom, views, y, {}), gt
@@ -192,17 +194,23 @@ def random_init(prob: Problem, n=50_000, seed=3005, s_lo=0.004, s_hi=0.03):
 
 
 def reconstruct(prob: Problem, gt, max_iters=5000, target_psnr=35.0, check_every=10, log=None,
-                t_start=None):
+                t_start=None, lr_final_frac=1.0, decay_iters=None):
     """Run fwd+bwd+Adam iterations until the volume PSNR against gt reaches
-    target_psnr (checked every check_every iterations) or max_iters.  Returns
-    a dict with the iteration count, seconds since t_start and the history."""
+    target_psnr (checked every check_every iterations) or max_iters.
+
+    lr_final_frac < 1 decays every rate exponentially to that fraction over
+    decay_iters iterations (default max_iters) and holds it there; the paper
+    decays its rate tenfold over training (sec. 5.1).  Returns a dict with
+    the iteration count, seconds since t_start and the history."""
     import time
     t0 = time.perf_counter() if t_start is None else t_start
     it = Iteration(prob)
+    decay_iters = decay_iters or max_iters
     psnr_out = torch.empty(3, dtype=torch.float64, device=prob.target.device)
     hist = []
     reached = None
     for i in range(1, max_iters + 1):
+        it.lr_factor = lr_final_frac ** (min(i - 1, decay_iters) / decay_iters)
         it.step()
         if i % check_every == 0 or i == max_iters:
             it.voxelize()
@@ -217,5 +225,8 @@ def reconstruct(prob: Problem, gt, max_iters=5000, target_psnr=35.0, check_every
             if val >= target_psnr:
                 reached = i
                 break
+    best = max(hist, key=lambda h: h[2]) if hist else None
     return {"iterations": reached, "seconds": (time.perf_counter() - t0) if reached else None,
-            "final_psnr": hist[-1][2] if hist else None, "history": hist}
+            "final_psnr": hist[-1][2] if hist else None,
+            "best_psnr": best[2] if best else None, "best_iter": best[0] if best else None,
+            "history": hist}
