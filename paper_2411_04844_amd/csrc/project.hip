@@ -20,10 +20,11 @@
 // Backward: one work-group per 16^3-cell brick accumulates, over all views, the
 // samples whose trilinear cell lies in the brick into a 17^3 LDS tile (no
 // global atomics); the tiles are then summed per voxel.  The LDS sums are
-// 64-bit fixed point: every contribution is scaled by a power of two S chosen
-// from max|proj| so that it fits in 32 bits, truncated to an integer and added
-// with ds_add_u64.  On gfx950 that is ~20x faster than ds_add_f32, and integer
-// addition makes the result independent of the order of the adds.
+// 64-bit fixed point: the weights of the samples of one ray in one cell are
+// summed in registers, scaled by a power of two S chosen from max|proj| so that
+// the sum fits in 32 bits, truncated to an integer and added with ds_add_u64.
+// Integer addition makes the result independent of the order of the adds
+// between rays (the order within a ray is fixed).
 #include <algorithm>
 #include <cmath>
 
@@ -387,85 +388,266 @@ __global__ __launch_bounds__(256) void absmax_bits(const float *__restrict__ x, 
     if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
 }
 
-// Fixed-point scale: the largest power of two S with |proj| * |scale| * S < 2^30.
-__device__ __forceinline__ float fixed_scale(const unsigned *maxbits, float scale) {
+// Fixed-point scale: the largest power of two S with
+// |proj| * |scale| * S * 2^headroom < 2^30, so that a sum of up to 2^headroom
+// weighted values still converts to a 32-bit integer.
+__device__ __forceinline__ float fixed_scale(const unsigned *maxbits, float scale, int headroom) {
     const float mc = __uint_as_float(*maxbits) * fabsf(scale);
     if (!(mc > 0.0f) || !(mc < 3.0e38f)) return 1.0f;
     int e;
     frexpf(mc, &e);  // mc < 2^e
-    return ldexpf(1.0f, 30 - e);
+    return ldexpf(1.0f, 30 - e - headroom);
 }
 
-// One work-group per brick.  For every view, each thread takes candidate rays
-// of the brick's shadow rectangle, finds the samples whose trilinear cell lies
-// in the brick (cell test on the same binary32 position as the projector), and
-// adds the eight weighted values, in fixed point, into the LDS tile.
+// ---- brick backprojection ---------------------------------------------------
+// One work-group per brick, two phases repeated until every view is done.
+//  1. Ray set-up: each thread takes one candidate pixel of a view's shadow
+//     rectangle, computes its ray and the exact range [k0, k1] of samples whose
+//     trilinear cell lies in the brick, and appends a 32-byte record to an LDS
+//     queue, plus one entry per segment of at most L consecutive samples.
+//  2. March: the work-group's lanes take the queued segments in order, so every
+//     lane runs (nearly) the same number of samples whatever the chord lengths
+//     of the rays, and add the eight weighted values of each sample, in fixed
+//     point, into the LDS tile.
+// The queue spans views; it is drained when it may not hold another chunk.
+constexpr int kChunk = 256;     // candidates per set-up pass (one per thread)
+constexpr int kRayCap = 1024;   // queued rays
+constexpr int kSegCap = 4096;   // queued segments
+constexpr int kMaxSeg = 8;      // segments per ray (the host sizes L for this)
+
+struct alignas(16) RayRec {  // 32 bytes
+    unsigned ulo[3];  // low words of the brick-relative 32.32 position of sample k0
+    float gr;         // weighted projection value, scaled to fixed point
+    unsigned dlo[3];  // low words of the 32.32 advance per sample
+    unsigned meta;    // [0,12): high words of the position, 4 bits per axis, in [0, 16)
+                      // [12,24): high words of the advance, 4-bit two's complement
+                      // [24,32): number of samples - 1
+};
+
+__device__ __forceinline__ bool in_brick(long long x, long long y, long long z) {
+    return (unsigned long long)x < (16ull << 32) && (unsigned long long)y < (16ull << 32) &&
+           (unsigned long long)z < (16ull << 32);
+}
+
+__device__ __forceinline__ int wave_excl_scan(int v, int lane, int *total) {
+    int incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int n = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += n;
+    }
+    *total = __shfl(incl, 63, 64);
+    return incl - v;
+}
+
+__device__ __forceinline__ void flush_cell(unsigned long long *tile, int lx, int ly, int lz,
+                                           const float (&e)[8]) {
+    unsigned long long *q = tile + (lz * kBT + ly) * kBT + lx;
+    atomicAdd(q, (unsigned long long)(long long)(int)e[0]);
+    atomicAdd(q + 1, (unsigned long long)(long long)(int)e[1]);
+    atomicAdd(q + kBT, (unsigned long long)(long long)(int)e[2]);
+    atomicAdd(q + kBT + 1, (unsigned long long)(long long)(int)e[3]);
+    atomicAdd(q + kBT * kBT, (unsigned long long)(long long)(int)e[4]);
+    atomicAdd(q + kBT * kBT + 1, (unsigned long long)(long long)(int)e[5]);
+    atomicAdd(q + kBT * kBT + kBT, (unsigned long long)(long long)(int)e[6]);
+    atomicAdd(q + kBT * kBT + kBT + 1, (unsigned long long)(long long)(int)e[7]);
+}
+
+// Phase 2 over the queued segments: lane i of wave w takes segments
+// w * 64 + i, w * 64 + i + 256, ...  Consecutive samples of a ray often share
+// their trilinear cell (about two per cell at half-voxel steps); a lane sums
+// their eight corner weights in registers and adds them to the tile once per
+// cell visit.  The fixed-point scale leaves room for the largest number of
+// samples one cell can hold.
+__device__ __forceinline__ void march_segments(unsigned long long *tile, const RayRec *rays,
+                                               const unsigned short *segs, int nsegs, int seg_len) {
+    const int t = threadIdx.x;
+    // Lane order within each block of 256 segments is strided by 32: a ray's
+    // segments are queued together and neighbouring pixels one after the
+    // other, so lanes side by side take segments of rays ~8 pixels apart and
+    // rarely add into the same LDS word at once.
+    const int perm = ((t & 7) << 5) | (t >> 3);
+    for (int base = 0; base < nsegs; base += 256) {
+        const int s = base + perm;
+        if (s >= nsegs) continue;
+        const unsigned e = segs[s];
+        const RayRec rec = rays[e >> 3];
+        const int seg = (int)(e & 7u);
+        const unsigned m = rec.meta;
+        long long ux = (long long)(((unsigned long long)(m & 15u) << 32) | rec.ulo[0]);
+        long long uy = (long long)(((unsigned long long)((m >> 4) & 15u) << 32) | rec.ulo[1]);
+        long long uz = (long long)(((unsigned long long)((m >> 8) & 15u) << 32) | rec.ulo[2]);
+        const long long dx = (long long)(((unsigned long long)(long long)((int)(m << 16) >> 28) << 32) | rec.dlo[0]);
+        const long long dy = (long long)(((unsigned long long)(long long)((int)(m << 12) >> 28) << 32) | rec.dlo[1]);
+        const long long dz = (long long)(((unsigned long long)(long long)((int)(m << 8) >> 28) << 32) | rec.dlo[2]);
+        const int n = (int)(m >> 24) + 1;
+        const int k_off = seg * seg_len;
+        const int cnt = min(seg_len, n - k_off);
+        ux += (long long)k_off * dx;
+        uy += (long long)k_off * dy;
+        uz += (long long)k_off * dz;
+        const float gr = rec.gr;
+        int cx = (int)(ux >> 32), cy = (int)(uy >> 32), cz = (int)(uz >> 32);
+        float acc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        for (int i = 0; i < cnt; ++i) {
+            const int lx = (int)(ux >> 32), ly = (int)(uy >> 32), lz = (int)(uz >> 32);
+            const float wx = (float)(unsigned)ux * kInv32;
+            const float wy = (float)(unsigned)uy * kInv32;
+            const float wz = (float)(unsigned)uz * kInv32;
+            ux += dx;
+            uy += dy;
+            uz += dz;
+            if (lx != cx || ly != cy || lz != cz) {
+                flush_cell(tile, cx, cy, cz, acc);
+#pragma unroll
+                for (int c = 0; c < 8; ++c) acc[c] = 0.0f;
+                cx = lx;
+                cy = ly;
+                cz = lz;
+            }
+            const float z1 = gr * wz, z0 = gr - z1;
+            const float y01 = z0 * wy, y00 = z0 - y01, y11 = z1 * wy, y10 = z1 - y11;
+            const float a0 = y00 * wx, a1 = y01 * wx, a2 = y10 * wx, a3 = y11 * wx;
+            acc[0] += y00 - a0;
+            acc[1] += a0;
+            acc[2] += y01 - a1;
+            acc[3] += a1;
+            acc[4] += y10 - a2;
+            acc[5] += a2;
+            acc[6] += y11 - a3;
+            acc[7] += a3;
+        }
+        flush_cell(tile, cx, cy, cz, acc);
+    }
+}
+
+// seg_len: samples per segment, chosen on the host so that no ray in a brick
+// has more than kMaxSeg segments (and no more than 256 samples).
 __global__ __launch_bounds__(256) void backproject_bricks(const float *__restrict__ proj, DevGrid g,
                                                           GeomDev G, Bricks bk,
                                                           const ushort4 *__restrict__ rect,
                                                           float eps, const unsigned *__restrict__ maxbits,
+                                                          int seg_len, int headroom,
                                                           long long *__restrict__ staging) {
     __shared__ unsigned long long tile[kBT3];
-    const int t = threadIdx.x;
+    __shared__ RayRec rays[kRayCap];
+    __shared__ unsigned short segs[kSegCap];
+    __shared__ int q_rays, q_segs;
+    const int t = threadIdx.x, lane = t & 63;
     const int64_t b = blockIdx.x;
     const int64_t nb = bk.count();
     const int bx = (int)(b % bk.nx), by = (int)((b / bk.nx) % bk.ny), bz = (int)(b / ((int64_t)bk.nx * bk.ny));
     // brick cells in padded coordinates: [c0, c0 + kB)
     const int c0x = bx * kB - 1 + kPad, c0y = by * kB - 1 + kPad, c0z = bz * kB - 1 + kPad;
+    const long long C0x = (long long)c0x << 32, C0y = (long long)c0y << 32, C0z = (long long)c0z << 32;
     // The candidate k-range is exact in binary64 for the brick grown by eps, a
-    // bound on |fixed-point position - binary64 position|; the cell test on the
-    // fixed-point position then assigns every sample to exactly one brick.
+    // bound on |fixed-point position - binary64 position|, so it holds every
+    // sample whose fixed-point cell is in the brick.  Those samples form one
+    // run of k (each axis test is an interval of the exact integer positions);
+    // the run's ends are found by testing the fixed-point cells.
     const double blo[3] = {c0x - (double)eps, c0y - (double)eps, c0z - (double)eps};
     const double bhi[3] = {c0x + kB + (double)eps, c0y + kB + (double)eps, c0z + kB + (double)eps};
-    const float gs = G.scale * fixed_scale(maxbits, G.scale);  // |proj * gs| < 2^30
+    const float gs = G.scale * fixed_scale(maxbits, G.scale, headroom);  // |proj * gs| < 2^(30 - headroom)
     for (int e = t; e < kBT3; e += 256) tile[e] = 0ull;
+    if (t == 0) {
+        q_rays = 0;
+        q_segs = 0;
+    }
     __syncthreads();
+    ushort4 rc_next = rect[b];
     for (int j = 0; j < G.n_views; ++j) {
-        const ushort4 rc = rect[(int64_t)j * nb + b];
+        const ushort4 rc = rc_next;
+        if (j + 1 < G.n_views) rc_next = rect[(int64_t)(j + 1) * nb + b];  // prefetch
         const int nu_r = (int)rc.y - (int)rc.x + 1, nv_r = (int)rc.w - (int)rc.z + 1;
         const int ncand = (nu_r > 0 && nv_r > 0) ? nu_r * nv_r : 0;
-        // Each thread takes a contiguous run of candidates, so the rays that a
-        // wave processes at the same time are several pixels apart and rarely
-        // add into the same LDS word.
-        const int per = (ncand + 255) / 256;
-        for (int i = 0; i < per; ++i) {
-            const int c = t * per + i;
-            if (c >= ncand) break;
-            const int iv = (int)rc.z + c / nu_r, iu = (int)rc.x + c % nu_r;
-            const float gr = gs * proj[((int64_t)j * G.nv + iv) * G.nu + iu];
-            if (gr == 0.0f) continue;
-            Ray r;
-            ray_geom(G, g, j, iu, iv, r);
-            int k0, k1;
-            if (!k_interval_coarse(r, blo, bhi, &k0, &k1)) continue;
-            long long ux = r.U[0] + (long long)k0 * r.DU[0];
-            long long uy = r.U[1] + (long long)k0 * r.DU[1];
-            long long uz = r.U[2] + (long long)k0 * r.DU[2];
-            for (int k = k0; k <= k1; ++k) {
-                const int lx = (int)(ux >> 32) - c0x, ly = (int)(uy >> 32) - c0y, lz = (int)(uz >> 32) - c0z;
-                const float wx = (float)(unsigned)ux * kInv32;
-                const float wy = (float)(unsigned)uy * kInv32;
-                const float wz = (float)(unsigned)uz * kInv32;
-                ux += r.DU[0];
-                uy += r.DU[1];
-                uz += r.DU[2];
-                if ((unsigned)lx >= (unsigned)kB || (unsigned)ly >= (unsigned)kB || (unsigned)lz >= (unsigned)kB)
-                    continue;
-                const float z1 = gr * wz, z0 = gr - z1;
-                const float y01 = z0 * wy, y00 = z0 - y01, y11 = z1 * wy, y10 = z1 - y11;
-                const float a0 = y00 * wx, a1 = y01 * wx, a2 = y10 * wx, a3 = y11 * wx;
-                unsigned long long *q = tile + (lz * kBT + ly) * kBT + lx;
-                atomicAdd(q, (unsigned long long)(long long)(int)(y00 - a0));
-                atomicAdd(q + 1, (unsigned long long)(long long)(int)a0);
-                atomicAdd(q + kBT, (unsigned long long)(long long)(int)(y01 - a1));
-                atomicAdd(q + kBT + 1, (unsigned long long)(long long)(int)a1);
-                atomicAdd(q + kBT * kBT, (unsigned long long)(long long)(int)(y10 - a2));
-                atomicAdd(q + kBT * kBT + 1, (unsigned long long)(long long)(int)a2);
-                atomicAdd(q + kBT * kBT + kBT, (unsigned long long)(long long)(int)(y11 - a3));
-                atomicAdd(q + kBT * kBT + kBT + 1, (unsigned long long)(long long)(int)a3);
+        for (int cb = 0; cb < ncand; cb += kChunk) {
+            // ---- phase 1: one candidate ray per thread (consecutive pixels of
+            // the rectangle, so the projection reads coalesce).  The read is
+            // issued first; the ray set-up hides its latency.
+            const int c = cb + t;
+            int n = 0;
+            RayRec rec;
+            if (c < ncand) {
+                const int iv = (int)rc.z + c / nu_r, iu = (int)rc.x + c % nu_r;
+                const float pv = proj[((int64_t)j * G.nv + iv) * G.nu + iu];
+                Ray r;
+                int k0, k1;
+                ray_geom(G, g, j, iu, iv, r);
+                const float gr = gs * pv;
+                if (gr != 0.0f) {
+                    if (k_interval_coarse(r, blo, bhi, &k0, &k1)) {
+                        long long ux = r.U[0] + (long long)k0 * r.DU[0] - C0x;
+                        long long uy = r.U[1] + (long long)k0 * r.DU[1] - C0y;
+                        long long uz = r.U[2] + (long long)k0 * r.DU[2] - C0z;
+                        while (k0 <= k1 && !in_brick(ux, uy, uz)) {
+                            ++k0;
+                            ux += r.DU[0];
+                            uy += r.DU[1];
+                            uz += r.DU[2];
+                        }
+                        if (k0 <= k1) {
+                            long long vx = r.U[0] + (long long)k1 * r.DU[0] - C0x;
+                            long long vy = r.U[1] + (long long)k1 * r.DU[1] - C0y;
+                            long long vz = r.U[2] + (long long)k1 * r.DU[2] - C0z;
+                            while (!in_brick(vx, vy, vz)) {  // stops at k0 at the latest
+                                --k1;
+                                vx -= r.DU[0];
+                                vy -= r.DU[1];
+                                vz -= r.DU[2];
+                            }
+                            n = k1 - k0 + 1;
+                            rec.ulo[0] = (unsigned)ux;
+                            rec.ulo[1] = (unsigned)uy;
+                            rec.ulo[2] = (unsigned)uz;
+                            rec.dlo[0] = (unsigned)r.DU[0];
+                            rec.dlo[1] = (unsigned)r.DU[1];
+                            rec.dlo[2] = (unsigned)r.DU[2];
+                            rec.gr = gr;
+                            rec.meta = (unsigned)(ux >> 32) | ((unsigned)(uy >> 32) << 4) |
+                                       ((unsigned)(uz >> 32) << 8) |
+                                       (((unsigned)(r.DU[0] >> 32) & 15u) << 12) |
+                                       (((unsigned)(r.DU[1] >> 32) & 15u) << 16) |
+                                       (((unsigned)(r.DU[2] >> 32) & 15u) << 20) |
+                                       ((unsigned)(n - 1) << 24);
+                        }
+                    }
+                }
+            }
+            const int nseg = (n + seg_len - 1) / seg_len;
+            const unsigned long long mask = __ballot(n > 0);
+            const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                                       __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+            int seg_tot;
+            const int seg_pre = wave_excl_scan(nseg, lane, &seg_tot);
+            int rbase = 0, sbase = 0;
+            if (lane == 0 && mask != 0ull) {
+                rbase = atomicAdd(&q_rays, __popcll(mask));
+                sbase = atomicAdd(&q_segs, seg_tot);
+            }
+            rbase = __shfl(rbase, 0, 64);
+            sbase = __shfl(sbase, 0, 64);
+            if (n > 0) {
+                const int slot = rbase + rank;
+                rays[slot] = rec;
+                for (int q = 0; q < nseg; ++q) segs[sbase + seg_pre + q] = (unsigned short)((slot << 3) | q);
+            }
+            __syncthreads();
+            const int nr = q_rays, ns = q_segs;
+            __syncthreads();  // every thread has read the counts before they change
+            if (nr > kRayCap - kChunk || ns > kSegCap - kChunk * kMaxSeg) {
+                // ---- phase 2
+                march_segments(tile, rays, segs, ns, seg_len);
+                __syncthreads();
+                if (t == 0) {
+                    q_rays = 0;
+                    q_segs = 0;
+                }
+                __syncthreads();
             }
         }
     }
+    const int ns = q_segs;
+    if (ns > 0) march_segments(tile, rays, segs, ns, seg_len);
     __syncthreads();
     long long *out = staging + b * kBT3;
     for (int e = t; e < kBT3; e += 256) out[e] = (long long)tile[e];
@@ -476,8 +658,8 @@ __global__ __launch_bounds__(256) void backproject_bricks(const float *__restric
 // entries divided by the fixed-point scale.
 __global__ __launch_bounds__(256) void gather_bricks(const long long *__restrict__ staging, DevGrid g,
                                                      Bricks bk, const unsigned *__restrict__ maxbits,
-                                                     float scale, float *__restrict__ V) {
-    const double inv_s = 1.0 / (double)fixed_scale(maxbits, scale);
+                                                     float scale, int headroom, float *__restrict__ V) {
+    const double inv_s = 1.0 / (double)fixed_scale(maxbits, scale, headroom);
     const int64_t total = (int64_t)g.nx * g.ny * g.nz;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
         const int64_t z = i / ((int64_t)g.nx * g.ny), rem = i - z * (int64_t)g.nx * g.ny;
@@ -638,6 +820,24 @@ extern "C" dgr_status dgr_backproject(const float *proj, const dgr_grid *grid,
     dgr_status s = check_proj(grid, geom, ws, ws_bytes);
     if (s != DGR_OK) return s;
     DGR_CHECK(proj && volume, "null projection or volume pointer");
+    // Samples of one ray inside a 16-cell brick: along the axis where the unit
+    // direction is largest (>= 1/sqrt(3)) a sample advances by at least
+    // step * min(inv_h) / sqrt(3) cells.  The queue records hold at most 256
+    // samples per ray and advances below 8 cells per sample per axis.
+    double min_inv = 1e300, max_inv = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        min_inv = std::min(min_inv, (double)grid->inv_h[a]);
+        max_inv = std::max(max_inv, (double)grid->inv_h[a]);
+    }
+    const double step_min = (double)geom->step * min_inv;
+    const int max_n = (int)std::min(1e9, std::floor(kB * std::sqrt(3.0) * 1.0001 / step_min) + 2.0);
+    DGR_CHECK(max_n <= 256, "backprojection needs step >= 0.11 voxel (got %.4g)", step_min);
+    DGR_CHECK((double)geom->step * max_inv <= 7.9, "backprojection needs step <= 7.9 voxels");
+    const int seg_len = std::max(8, (max_n + kMaxSeg - 1) / kMaxSeg);
+    // samples of one ray inside one unit cell: at most sqrt(3) / step + 1
+    const int per_cell = (int)std::floor(std::sqrt(3.0) * 1.0001 / step_min) + 1;
+    int headroom = 0;
+    while ((1 << headroom) < per_cell) ++headroom;
     hipStream_t st = as_stream(stream);
     ProjWs w = carve_proj_ws(ws, grid, geom);
     DevGrid g = dev_grid(grid);
@@ -656,11 +856,12 @@ extern "C" dgr_status dgr_backproject(const float *proj, const dgr_grid *grid,
         proj, nproj, w.maxbits);
     DGR_LAUNCH_CHECK();
     backproject_bricks<<<dim3((unsigned)bk.count()), dim3(256), 0, st>>>(proj, g, G, bk, w.rect, eps,
-                                                                         w.maxbits, w.staging);
+                                                                         w.maxbits, seg_len, headroom,
+                                                                         w.staging);
     DGR_LAUNCH_CHECK();
     const int64_t nvox = (int64_t)grid->dims[0] * grid->dims[1] * grid->dims[2];
     gather_bricks<<<dim3(grid_stride_blocks(nvox)), dim3(256), 0, st>>>(w.staging, g, bk, w.maxbits,
-                                                                        G.scale, volume);
+                                                                        G.scale, headroom, volume);
     DGR_LAUNCH_CHECK();
     return DGR_OK;
 }
