@@ -39,6 +39,11 @@ What pins each function (tests under ``tests/test_oracle_*.py``):
   by the discrete Ram-Lak response of a single impulse.
 * ``init_from_volume`` -- pinned by brute-force inverse-CDF sampling in
   numpy and by the sampling frequencies of a two-voxel volume.
+* ``oracle.unet`` (numpy, binary64) -- the learned-initialisation network:
+  3x3x3 convolution against a seven-loop brute force and the impulse
+  response, its backward against the adjoint identities, pooling/upsampling
+  against theirs, the network and loss gradients against central
+  differences (see that module's header).
 """
 from __future__ import annotations
 
