@@ -210,6 +210,62 @@ dgr_status dgr_init_from_volume(const float *volume, const dgr_grid *grid, float
 dgr_status dgr_fit_density_scale(const float *p1, const float *target, int64_t m, float *density,
                                  int64_t n, double *kappa, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- learned initialisation: a 3-D U-Net on the matrix cores -------------- */
+/* Not part of DGR (the paper initialises its Gaussians from an FBP/FDK volume,
+ * Fig. 4 caption, or at random): a network that maps a one-channel volume to
+ * per-voxel density, log-scale and occupancy-logit fields from which an
+ * initial Gaussian set is drawn; the plain initialisation stays the fallback.
+ *
+ * Network (base width B = 32, volume extents multiples of 8 in [8, 1024]):
+ *   enc1 = relu(conv3(x; 1->B)),  enc2 = relu(conv3(pool(enc1); B->2B)),
+ *   enc3 = relu(conv3(pool(enc2); 2B->4B)), bott = relu(conv3(pool(enc3); 4B->8B)),
+ *   dec3 = relu(conv3([up(bott), enc3]; 12B->4B)),
+ *   dec2 = relu(conv3([up(dec3), enc2]; 6B->2B)),
+ *   dec1 = relu(conv3([up(dec2), enc1]; 3B->B)),  out = head(dec1; B->3).
+ * conv3: 3x3x3 cross-correlation, zero padding 1; tap t = 9(dz+1)+3(dy+1)+(dx+1)
+ * multiplies x[z+dz][y+dy][x+dx].  pool: 2x2x2 mean.  up: nearest 2x.  [a, b]:
+ * channel concatenation.  head: 1x1x1 convolution.
+ * Parameters (binary32, flat): for enc1, enc2, enc3, bott, dec3, dec2, dec1 in
+ * turn W[27][Cout][Cin] then b[Cout]; then head W[3][B], b[3] (2,904,707 values).
+ * Activations and activation gradients are bfloat16, products accumulate in
+ * binary32.  Volumes are [nz][ny][nx] (x fastest); dims = {nx, ny, nz}; out
+ * is [nz][ny][nx][3] = (density, log-scale, occupancy logit).
+ * All pointers are DEVICE pointers; ws is 256-byte aligned and holds the
+ * activations: dgr_unet_backward must follow dgr_unet_forward with the same
+ * params, input, dims and ws on the same stream. */
+int64_t dgr_unet_param_count(int32_t base);  /* -1 if base is not 32 */
+size_t dgr_unet_workspace(const int32_t dims[3], int32_t base);  /* 0 if unsupported */
+dgr_status dgr_unet_forward(const float *params, const float *input, const int32_t dims[3],
+                            int32_t base, float *out, void *ws, size_t ws_bytes, void *stream);
+/* grad (binary32, flat like params) = d sum(dout * out) / d params. */
+dgr_status dgr_unet_backward(const float *params, const float *input, const int32_t dims[3],
+                             int32_t base, const float *dout, float *grad, void *ws,
+                             size_t ws_bytes, void *stream);
+/* Training loss over n voxels, target [n][3] = (t_d, t_s, t_o), t_o in [0, 1]:
+ * L = mean (o_d - t_d)^2 + mean t_o (o_s - t_s)^2 + mean (softplus(o_o) - t_o o_o);
+ * *loss (DEVICE binary32) and dout = dL/dout [n][3]. */
+size_t dgr_unet_loss_workspace(void);
+dgr_status dgr_unet_loss(const float *out, const float *target, int64_t n_voxels, float *loss,
+                         float *dout, void *ws, size_t ws_bytes, void *stream);
+
+/* One conv3 layer on the matrix cores (the network's building block).
+ * x: bfloat16 [nz][ny][nx][x_stride] (channels 0..cin-1 read); w: bfloat16
+ * [27][cout][cin]; bias: binary32 [cout] or NULL; y: bfloat16
+ * [nz][ny][nx][y_stride] (channels 0..cout-1 written, rounded to nearest
+ * even), relu != 0 clamps at zero.  cin, cout multiples of 32; strides
+ * multiples of 8; x, w, y 16-byte aligned. */
+dgr_status dgr_conv3_forward(const uint16_t *x, int32_t x_stride, const int32_t dims[3],
+                             int32_t cin, const uint16_t *w, const float *bias, int32_t cout,
+                             int32_t relu, uint16_t *y, int32_t y_stride, void *stream);
+/* Backward of y = conv3(x; w) + b for dy (bfloat16 [nz][ny][nx][cout]):
+ * dw (binary32 [27][cout][cin]), db (binary32 [cout]) and dx (bfloat16
+ * [nz][ny][nx][cin]).  w is binary32 here (rounded to bfloat16 inside). */
+size_t dgr_conv3_grad_workspace(const int32_t dims[3], int32_t cin, int32_t cout);
+dgr_status dgr_conv3_backward(const uint16_t *x, int32_t x_stride, const int32_t dims[3],
+                              int32_t cin, const float *w, const uint16_t *dy, int32_t cout,
+                              float *dw, float *db, uint16_t *dx, void *ws, size_t ws_bytes,
+                              void *stream);
+
 /* ---- binary64 path for finite-difference gradient checks ------------------ */
 
 /* The volume of dgr_voxelize evaluated in binary64 (parameters promoted

@@ -1,0 +1,892 @@
+// Learned initialisation: a 3-D U-Net that maps a one-channel volume (an FDK
+// reconstruction) to per-voxel density, log-scale and occupancy fields, from
+// which an initial Gaussian set is drawn.  The paper initialises its Gaussians
+// from an FBP/FDK volume (Fig. 4 caption) or at random; the network proposes
+// a better-placed set, and the plain initialisation remains the fallback.
+//
+// Architecture (base width B = 32; extents divisible by 8):
+//   enc1 = relu(conv3(x; 1 -> B))                       D
+//   enc2 = relu(conv3(pool(enc1); B -> 2B))             D/2
+//   enc3 = relu(conv3(pool(enc2); 2B -> 4B))            D/4
+//   bott = relu(conv3(pool(enc3); 4B -> 8B))            D/8
+//   dec3 = relu(conv3([up(bott), enc3]; 12B -> 4B))     D/4
+//   dec2 = relu(conv3([up(dec3), enc2]; 6B -> 2B))      D/2
+//   dec1 = relu(conv3([up(dec2), enc1]; 3B -> B))       D
+//   out  = head(dec1; B -> 3)                           1x1x1
+// conv3: 3x3x3 cross-correlation, zero padding 1, tap t = 9(dz+1)+3(dy+1)+(dx+1).
+// pool: 2x2x2 mean; up: nearest 2x; [a, b]: channel concatenation.
+//
+// Numerics: activations, activation gradients and the weights fed to the
+// matrix cores are bfloat16 (round to nearest even); every product is
+// accumulated in binary32 (MFMA f32 accumulators); weight gradients and the
+// head are binary32.
+//
+// Data layout: channels-last [z][y][x][c].  Each skip concatenation is one
+// buffer: the encoder writes its output straight into the channel slice that
+// the decoder reads, so concatenation costs nothing.
+//
+// Kernels:
+//   conv3_mfma   implicit GEMM (M = voxels, N = output channels,
+//                K = 27 x input channels) on v_mfma_f32_16x16x32_bf16; A and B
+//                fragments are loaded straight from memory (8 contiguous
+//                channels per lane).  The data gradient is the same kernel
+//                with transposed, tap-reversed weights.
+//   conv3_wgrad  dW[t] = dY^T shift_t(X): K = voxels, so 64-voxel tiles of
+//                both operands are transposed through LDS; split over voxel
+//                chunks into binary32 partials summed in a fixed order.
+//   conv1_*      the 1-channel first layer on the VALU (K = 27).
+//   pooling, upsampling (with the ReLU masks of the backward fused in), the
+//   1x1 head and the loss are elementwise VALU kernels.
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+
+namespace dgr {
+namespace {
+
+typedef unsigned short u16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ u16 f2bf(float f) {
+    unsigned u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    return (u16)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(u16 h) { return __uint_as_float((unsigned)h << 16); }
+
+struct Vol {
+    int nx, ny, nz;
+    int64_t V;
+};
+
+__device__ __forceinline__ void vox_coords(const Vol &d, int64_t v, int *x, int *y, int *z) {
+    const int64_t plane = (int64_t)d.nx * d.ny;
+    *z = (int)(v / plane);
+    const int64_t r = v - (int64_t)(*z) * plane;
+    *y = (int)(r / d.nx);
+    *x = (int)(r - (int64_t)(*y) * d.nx);
+}
+
+// ---- implicit-GEMM 3x3x3 convolution on the matrix cores ---------------------
+// Work-group: 256 voxels (4 waves x 64) x 16*NT output channels.  Each wave
+// holds 4 x NT accumulator tiles of 16x16.  Lane l of a wave owns rows
+// (voxels) l%16 + 16 m of A and columns l%16 + 16 n of B; its 8-element
+// K slice is 8 (l/16) .. 8 (l/16) + 7 within each 32-channel K block.
+// x: bf16 [V][xs] (channels 0..cin-1 used); w: bf16 [27][cout][cin];
+// y: bf16 [V][ys] (channels 0..cout-1 written).  cin % 32 == 0, xs % 8 == 0,
+// ys % 8 == 0, pointers 16-byte aligned.
+template <int NT>
+__global__ __launch_bounds__(256) void conv3_mfma(const u16 *__restrict__ x, int xs, Vol d, int cin,
+                                                  const u16 *__restrict__ w,
+                                                  const float *__restrict__ bias, int cout, int relu,
+                                                  u16 *__restrict__ y, int ys) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    const int64_t vbase = ((int64_t)blockIdx.x * 4 + wave) * 64;
+    const int co0 = blockIdx.y * (16 * NT);
+    int vx[4], vy[4], vz[4];
+    bool vin[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int64_t v = vbase + m * 16 + r;
+        vin[m] = v < d.V;
+        vox_coords(d, vin[m] ? v : 0, &vx[m], &vy[m], &vz[m]);
+    }
+    f32x4 acc[4][NT];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const bf16x8 zero = __builtin_bit_cast(bf16x8, u32x4{0u, 0u, 0u, 0u});
+    for (int t = 0; t < 27; ++t) {
+        const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+        const u16 *xp[4];
+        bool ok[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int xx = vx[m] + dx, yy = vy[m] + dy, zz = vz[m] + dz;
+            ok[m] = vin[m] && xx >= 0 && yy >= 0 && zz >= 0 && xx < d.nx && yy < d.ny && zz < d.nz;
+            const int64_t vn = ok[m] ? ((int64_t)zz * d.ny + yy) * d.nx + xx : 0;
+            xp[m] = x + vn * xs + 8 * g;
+        }
+        const u16 *wp = w + ((int64_t)t * cout + co0 + r) * cin + 8 * g;
+        for (int kb = 0; kb < cin; kb += 32) {
+            bf16x8 a[4], b[NT];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) a[m] = ok[m] ? *reinterpret_cast<const bf16x8 *>(xp[m] + kb) : zero;
+#pragma unroll
+            for (int n = 0; n < NT; ++n) b[n] = *reinterpret_cast<const bf16x8 *>(wp + (int64_t)n * 16 * cin + kb);
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int n = 0; n < NT; ++n)
+                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b[n], acc[m][n], 0, 0, 0);
+        }
+    }
+    // lane holds D[4 g + i][r] of every tile: voxel vbase + 16 m + 4 g + i,
+    // channel co0 + 16 n + r
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+        const int co = co0 + n * 16 + r;
+        const float bb = bias ? bias[co] : 0.0f;
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t v = vbase + m * 16 + 4 * g + i;
+                if (v < d.V) {
+                    float val = acc[m][n][i] + bb;
+                    if (relu) val = fmaxf(val, 0.0f);
+                    y[v * ys + co] = f2bf(val);
+                }
+            }
+    }
+}
+
+// ---- weight gradient ------------------------------------------------------------
+// Grid: x = 27 taps x (cout / 32) x (cin / 32) tiles, y = voxel chunks.  Each
+// work-group accumulates dW[t][co0 .. co0+31][ci0 .. ci0+31] over its chunk:
+// per 64-voxel step it stages dY[v][co] and X[v + t][ci] transposed in LDS
+// ([channel][voxel], so the K = voxel slice of a lane is contiguous); wave w
+// owns the 16x16 sub-tile (co0 + 16 (w / 2), ci0 + 16 (w % 2)).
+constexpr int kWgStep = 64;
+constexpr int kWgPitch = kWgStep + 8;  // u16 per LDS row (144 bytes, 16-byte aligned)
+
+__global__ __launch_bounds__(256) void conv3_wgrad(const u16 *__restrict__ x, int xs, Vol d, int cin,
+                                                   const u16 *__restrict__ dy, int dys, int cout,
+                                                   int64_t chunk, float *__restrict__ part) {
+    __shared__ __attribute__((aligned(16))) u16 At[32 * kWgPitch];  // [co][v]
+    __shared__ __attribute__((aligned(16))) u16 Bt[32 * kWgPitch];  // [ci][v]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    const int n_ci = cin / 32, n_co = cout / 32;
+    int tile = blockIdx.x;
+    const int ib = tile % n_ci;
+    tile /= n_ci;
+    const int cb = tile % n_co;
+    const int t = tile / n_co;
+    const int dz = t / 9 - 1, dyy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+    const int64_t v_begin = (int64_t)blockIdx.y * chunk;
+    const int64_t v_end = min(d.V, v_begin + chunk);
+    const int msub = (wave >> 1) * 16, nsub = (wave & 1) * 16;
+    f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    // loader: thread tid stages 8 channels (c8 = 8 (tid % 4)) of voxel tid / 4
+    // of dY, and the same of X[v + t]
+    const int lv = tid >> 2, c8 = (tid & 3) * 8;
+    for (int64_t v0 = v_begin; v0 < v_end; v0 += kWgStep) {
+        const int64_t v = v0 + lv;
+        u32x4 qa = u32x4{0u, 0u, 0u, 0u}, qb = u32x4{0u, 0u, 0u, 0u};
+        if (lv < kWgStep && v < v_end) {
+            qa = *reinterpret_cast<const u32x4 *>(dy + v * dys + cb * 32 + c8);
+            int px, py, pz;
+            vox_coords(d, v, &px, &py, &pz);
+            const int xx = px + dx, yy = py + dyy, zz = pz + dz;
+            if (xx >= 0 && yy >= 0 && zz >= 0 && xx < d.nx && yy < d.ny && zz < d.nz) {
+                const int64_t vn = ((int64_t)zz * d.ny + yy) * d.nx + xx;
+                qb = *reinterpret_cast<const u32x4 *>(x + vn * xs + ib * 32 + c8);
+            }
+        }
+        if (lv < kWgStep) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                At[(c8 + 2 * j) * kWgPitch + lv] = (u16)(qa[j] & 0xffffu);
+                At[(c8 + 2 * j + 1) * kWgPitch + lv] = (u16)(qa[j] >> 16);
+                Bt[(c8 + 2 * j) * kWgPitch + lv] = (u16)(qb[j] & 0xffffu);
+                Bt[(c8 + 2 * j + 1) * kWgPitch + lv] = (u16)(qb[j] >> 16);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kWgStep; kk += 32) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(At + (msub + r) * kWgPitch + kk + 8 * g);
+            const bf16x8 b = *reinterpret_cast<const bf16x8 *>(Bt + (nsub + r) * kWgPitch + kk + 8 * g);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // lane holds D[4 g + i][r]: co = cb*32 + msub + 4g + i, ci = ib*32 + nsub + r
+    float *out = part + ((int64_t)blockIdx.y * 27 + t) * cout * cin;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int co = cb * 32 + msub + 4 * g + i, ci = ib * 32 + nsub + r;
+        out[(int64_t)co * cin + ci] = acc[i];
+    }
+}
+
+// out[i] = sum_{c < n_chunks} part[c][i] (fixed order).
+__global__ __launch_bounds__(256) void sum_chunks(const float *__restrict__ part, int n_chunks, int64_t n,
+                                                  float *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.0f;
+    for (int c = 0; c < n_chunks; ++c) s += part[(int64_t)c * n + i];
+    out[i] = s;
+}
+
+// Per-channel sums of a bf16 [V][s] slice (channels 0..C-1), C <= 256:
+// part[block][c] over the block's voxel range.
+constexpr int kSumBlocks = 512;
+__global__ __launch_bounds__(256) void channel_sums(const u16 *__restrict__ a, int s, int C, int64_t V,
+                                                    float *__restrict__ part) {
+    const int c = threadIdx.x;
+    if (c >= C) return;
+    const int64_t per = (V + gridDim.x - 1) / gridDim.x;
+    const int64_t v0 = (int64_t)blockIdx.x * per, v1 = min(V, v0 + per);
+    float acc = 0.0f;
+    for (int64_t v = v0; v < v1; ++v) acc += bf2f(a[v * s + c]);
+    part[(int64_t)blockIdx.x * C + c] = acc;
+}
+
+// ---- first layer (one input channel) on the VALU ------------------------------------
+// y[v][c] = relu(b[c] + sum_t W[t][c] x[v + t]) for c < B (bf16 out, stride ys).
+__global__ __launch_bounds__(256) void conv1_fwd(const float *__restrict__ x, Vol d,
+                                                 const float *__restrict__ W /*[27][B]*/,
+                                                 const float *__restrict__ b, int B,
+                                                 u16 *__restrict__ y, int ys) {
+    __shared__ float sw[27 * 256];
+    __shared__ float sb[256];
+    for (int i = threadIdx.x; i < 27 * B; i += 256) sw[i] = W[i];
+    for (int i = threadIdx.x; i < B; i += 256) sb[i] = b[i];
+    __syncthreads();
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (v >= d.V) return;
+    int px, py, pz;
+    vox_coords(d, v, &px, &py, &pz);
+    float nb[27];
+#pragma unroll
+    for (int t = 0; t < 27; ++t) {
+        const int xx = px + t % 3 - 1, yy = py + (t / 3) % 3 - 1, zz = pz + t / 9 - 1;
+        const bool in = xx >= 0 && yy >= 0 && zz >= 0 && xx < d.nx && yy < d.ny && zz < d.nz;
+        nb[t] = in ? x[((int64_t)zz * d.ny + yy) * d.nx + xx] : 0.0f;
+    }
+    for (int c = 0; c < B; ++c) {
+        float acc = sb[c];
+#pragma unroll
+        for (int t = 0; t < 27; ++t) acc = fmaf(sw[t * B + c], nb[t], acc);
+        y[v * ys + c] = f2bf(fmaxf(acc, 0.0f));
+    }
+}
+
+// part[block][t][c] = sum over the block's voxels of dy[v][c] x[v + t]; the
+// block's 256 threads are 8 voxel lanes x 32 channel lanes (B <= 32 per pass).
+__global__ __launch_bounds__(256) void conv1_wgrad(const float *__restrict__ x, Vol d,
+                                                   const u16 *__restrict__ dy, int dys, int B,
+                                                   float *__restrict__ part) {
+    __shared__ float red[8][27][32];
+    const int c = threadIdx.x & 31, j = threadIdx.x >> 5;
+    const int64_t per = (d.V + gridDim.x - 1) / gridDim.x;
+    const int64_t v0 = (int64_t)blockIdx.x * per, v1 = min(d.V, v0 + per);
+    for (int cb = 0; cb < B; cb += 32) {
+        float acc[27];
+#pragma unroll
+        for (int t = 0; t < 27; ++t) acc[t] = 0.0f;
+        if (cb + c < B) {
+            for (int64_t v = v0 + j; v < v1; v += 8) {
+                const float g = bf2f(dy[v * dys + cb + c]);
+                int px, py, pz;
+                vox_coords(d, v, &px, &py, &pz);
+#pragma unroll
+                for (int t = 0; t < 27; ++t) {
+                    const int xx = px + t % 3 - 1, yy = py + (t / 3) % 3 - 1, zz = pz + t / 9 - 1;
+                    const bool in = xx >= 0 && yy >= 0 && zz >= 0 && xx < d.nx && yy < d.ny && zz < d.nz;
+                    acc[t] = fmaf(g, in ? x[((int64_t)zz * d.ny + yy) * d.nx + xx] : 0.0f, acc[t]);
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 27; ++t) red[j][t][c] = acc[t];
+        __syncthreads();
+        for (int i = threadIdx.x; i < 27 * 32; i += 256) {
+            const int t = i / 32, cc = i % 32;
+            float s = 0.0f;
+            for (int jj = 0; jj < 8; ++jj) s += red[jj][t][cc];
+            if (cb + cc < B) part[((int64_t)blockIdx.x * 27 + t) * B + cb + cc] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// ---- weights -----------------------------------------------------------------------------
+// wb[t][o][i] = bf16(W[t][o][i]); wt[t][i][o] = bf16(W[26 - t][o][i]) (the data
+// gradient is a convolution of dY with these transposed, tap-reversed weights).
+__global__ __launch_bounds__(256) void cast_weights(const float *__restrict__ W, int cout, int cin,
+                                                    u16 *__restrict__ wb, u16 *__restrict__ wt) {
+    const int64_t n = 27LL * cout * cin;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int t = (int)(i / ((int64_t)cout * cin));
+    const int rem = (int)(i - (int64_t)t * cout * cin);
+    const int o = rem / cin, ci = rem - o * cin;
+    const u16 h = f2bf(W[i]);
+    wb[i] = h;
+    wt[((int64_t)(26 - t) * cin + ci) * cout + o] = h;
+}
+
+// ---- pooling, upsampling, skip gradients ---------------------------------------------------
+// One thread per (coarse voxel, 8-channel group).  Fine volume d (even
+// extents), coarse volume dc = d / 2.
+__device__ __forceinline__ int64_t fine_child(const Vol &d, int cx, int cy, int cz, int k) {
+    return ((int64_t)(2 * cz + (k >> 2)) * d.ny + (2 * cy + ((k >> 1) & 1))) * d.nx + 2 * cx + (k & 1);
+}
+
+__global__ __launch_bounds__(256) void pool2_fwd(const u16 *__restrict__ a, int as, Vol d, Vol dc, int C,
+                                                 u16 *__restrict__ out) {
+    const int groups = C / 8;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= dc.V * groups) return;
+    const int64_t p = i / groups;
+    const int c8 = (int)(i - p * groups) * 8;
+    int cx, cy, cz;
+    vox_coords(dc, p, &cx, &cy, &cz);
+    float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < 8; ++k) {
+        const u32x4 q = *reinterpret_cast<const u32x4 *>(a + fine_child(d, cx, cy, cz, k) * as + c8);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            s[2 * j] += bf2f((u16)(q[j] & 0xffffu));
+            s[2 * j + 1] += bf2f((u16)(q[j] >> 16));
+        }
+    }
+    u32x4 o;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o[j] = (unsigned)f2bf(0.125f * s[2 * j]) | ((unsigned)f2bf(0.125f * s[2 * j + 1]) << 16);
+    *reinterpret_cast<u32x4 *>(out + p * C + c8) = o;
+}
+
+// out slice [V][os] channels 0..C-1 = src[parent][c]
+__global__ __launch_bounds__(256) void up2_fwd(const u16 *__restrict__ src, Vol d, Vol dc, int C,
+                                               u16 *__restrict__ out, int os) {
+    const int groups = C / 8;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= dc.V * groups) return;
+    const int64_t p = i / groups;
+    const int c8 = (int)(i - p * groups) * 8;
+    int cx, cy, cz;
+    vox_coords(dc, p, &cx, &cy, &cz);
+    const u32x4 q = *reinterpret_cast<const u32x4 *>(src + p * C + c8);
+    for (int k = 0; k < 8; ++k) *reinterpret_cast<u32x4 *>(out + fine_child(d, cx, cy, cz, k) * os + c8) = q;
+}
+
+// dpre[p][c] = (sum of the 8 children of dcat[.][c]) * (act[p][c] > 0)
+__global__ __launch_bounds__(256) void up2_bwd_relu(const u16 *__restrict__ dcat, int ds, Vol d, Vol dc,
+                                                    int C, const u16 *__restrict__ act,
+                                                    u16 *__restrict__ dpre) {
+    const int groups = C / 8;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= dc.V * groups) return;
+    const int64_t p = i / groups;
+    const int c8 = (int)(i - p * groups) * 8;
+    int cx, cy, cz;
+    vox_coords(dc, p, &cx, &cy, &cz);
+    float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < 8; ++k) {
+        const u32x4 q = *reinterpret_cast<const u32x4 *>(dcat + fine_child(d, cx, cy, cz, k) * ds + c8);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            s[2 * j] += bf2f((u16)(q[j] & 0xffffu));
+            s[2 * j + 1] += bf2f((u16)(q[j] >> 16));
+        }
+    }
+    const u32x4 m = *reinterpret_cast<const u32x4 *>(act + p * C + c8);
+    u32x4 o;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float a0 = bf2f((u16)(m[j] & 0xffffu)) > 0.0f ? s[2 * j] : 0.0f;
+        const float a1 = bf2f((u16)(m[j] >> 16)) > 0.0f ? s[2 * j + 1] : 0.0f;
+        o[j] = (unsigned)f2bf(a0) | ((unsigned)f2bf(a1) << 16);
+    }
+    *reinterpret_cast<u32x4 *>(dpre + p * C + c8) = o;
+}
+
+// dpre[v][c] = (dskip[v][c] + dpool[parent(v)][c] / 8) * (act[v][c] > 0);
+// dskip: slice of the concatenation gradient (stride ds), act: encoder output
+// (stride as).  One thread per (fine voxel, 8-channel group).
+__global__ __launch_bounds__(256) void skip_bwd_relu(const u16 *__restrict__ dskip, int ds,
+                                                     const u16 *__restrict__ dpool, Vol d, Vol dc, int C,
+                                                     const u16 *__restrict__ act, int as,
+                                                     u16 *__restrict__ dpre) {
+    const int groups = C / 8;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= d.V * groups) return;
+    const int64_t v = i / groups;
+    const int c8 = (int)(i - v * groups) * 8;
+    int px, py, pz;
+    vox_coords(d, v, &px, &py, &pz);
+    const int64_t p = ((int64_t)(pz >> 1) * dc.ny + (py >> 1)) * dc.nx + (px >> 1);
+    const u32x4 qs = *reinterpret_cast<const u32x4 *>(dskip + v * ds + c8);
+    const u32x4 qp = *reinterpret_cast<const u32x4 *>(dpool + p * C + c8);
+    const u32x4 m = *reinterpret_cast<const u32x4 *>(act + v * as + c8);
+    u32x4 o;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        float a0 = bf2f((u16)(qs[j] & 0xffffu)) + 0.125f * bf2f((u16)(qp[j] & 0xffffu));
+        float a1 = bf2f((u16)(qs[j] >> 16)) + 0.125f * bf2f((u16)(qp[j] >> 16));
+        if (!(bf2f((u16)(m[j] & 0xffffu)) > 0.0f)) a0 = 0.0f;
+        if (!(bf2f((u16)(m[j] >> 16)) > 0.0f)) a1 = 0.0f;
+        o[j] = (unsigned)f2bf(a0) | ((unsigned)f2bf(a1) << 16);
+    }
+    *reinterpret_cast<u32x4 *>(dpre + v * C + c8) = o;
+}
+
+// ---- head (1x1x1, B -> 3) and loss -----------------------------------------------------
+__global__ __launch_bounds__(256) void head_fwd(const u16 *__restrict__ a, int B, int64_t V,
+                                                const float *__restrict__ Wh, const float *__restrict__ bh,
+                                                float *__restrict__ out) {
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (v >= V) return;
+    float o0 = bh[0], o1 = bh[1], o2 = bh[2];
+    for (int c = 0; c < B; ++c) {
+        const float h = bf2f(a[v * B + c]);
+        o0 = fmaf(Wh[c], h, o0);
+        o1 = fmaf(Wh[B + c], h, o1);
+        o2 = fmaf(Wh[2 * B + c], h, o2);
+    }
+    out[3 * v] = o0;
+    out[3 * v + 1] = o1;
+    out[3 * v + 2] = o2;
+}
+
+// dpre[v][c] = (sum_o dout[v][o] Wh[o][c]) * (a[v][c] > 0); block partials of
+// dWh[o][c] = sum_v dout[v][o] a[v][c] and dbh[o] (B <= 256).
+__global__ __launch_bounds__(256) void head_bwd(const u16 *__restrict__ a, int B, int64_t V,
+                                                const float *__restrict__ Wh, const float *__restrict__ dout,
+                                                u16 *__restrict__ dpre, float *__restrict__ part) {
+    const int c = threadIdx.x;
+    const int64_t per = (V + gridDim.x - 1) / gridDim.x;
+    const int64_t v0 = (int64_t)blockIdx.x * per, v1 = min(V, v0 + per);
+    float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, b0 = 0.0f, b1 = 0.0f, b2 = 0.0f;
+    if (c < B) {
+        const float w0 = Wh[c], w1 = Wh[B + c], w2 = Wh[2 * B + c];
+        for (int64_t v = v0; v < v1; ++v) {
+            const float d0 = dout[3 * v], d1 = dout[3 * v + 1], d2 = dout[3 * v + 2];
+            const float h = bf2f(a[v * B + c]);
+            g0 = fmaf(d0, h, g0);
+            g1 = fmaf(d1, h, g1);
+            g2 = fmaf(d2, h, g2);
+            if (c == 0) {
+                b0 += d0;
+                b1 += d1;
+                b2 += d2;
+            }
+            const float s = fmaf(d0, w0, fmaf(d1, w1, d2 * w2));
+            dpre[v * B + c] = f2bf(h > 0.0f ? s : 0.0f);
+        }
+        float *o = part + (int64_t)blockIdx.x * (3 * B + 3);
+        o[c] = g0;
+        o[B + c] = g1;
+        o[2 * B + c] = g2;
+        if (c == 0) {
+            o[3 * B] = b0;
+            o[3 * B + 1] = b1;
+            o[3 * B + 2] = b2;
+        }
+    }
+}
+
+// part[block] = sum of per-voxel losses (binary64); dout = dL/dout.
+__global__ __launch_bounds__(256) void loss_kernel(const float *__restrict__ out,
+                                                   const float *__restrict__ tgt, int64_t V,
+                                                   float *__restrict__ dout, double *__restrict__ part) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    const float inv_v = (float)(1.0 / (double)V);
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < V; v += (int64_t)gridDim.x * 256) {
+        const float od = out[3 * v], os = out[3 * v + 1], oo = out[3 * v + 2];
+        const float td = tgt[3 * v], ts = tgt[3 * v + 1], to = tgt[3 * v + 2];
+        const float ed = od - td, es = os - ts;
+        const float sp = fmaxf(oo, 0.0f) + log1pf(expf(-fabsf(oo)));  // softplus
+        acc += (double)(ed * ed) + (double)(to * es * es) + (double)(sp - to * oo);
+        dout[3 * v] = 2.0f * ed * inv_v;
+        dout[3 * v + 1] = 2.0f * to * es * inv_v;
+        dout[3 * v + 2] = (1.0f / (1.0f + expf(-oo)) - to) * inv_v;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void loss_final(const double *__restrict__ part, int nb, int64_t V,
+                                                  float *__restrict__ loss) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256) acc += part[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = (float)(sh[0] / (double)V);
+}
+
+// out[i] = sum over blocks of part[block][i] (fixed order), n entries.
+__global__ __launch_bounds__(256) void sum_parts(const float *__restrict__ part, int nb, int n,
+                                                 float *__restrict__ out) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.0f;
+    for (int b = 0; b < nb; ++b) s += part[(int64_t)b * n + i];
+    out[i] = s;
+}
+
+// ---- host side -----------------------------------------------------------------------------
+unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+struct Layer {
+    int cin, cout;
+    int64_t w_off, b_off;  // offsets in the flat parameter vector
+};
+
+struct Net {
+    int B;
+    Vol d[4];  // levels 1..4 (index 0..3)
+    Layer L[8];  // enc1 enc2 enc3 bott dec3 dec2 dec1 head
+    int64_t n_params;
+};
+
+enum { ENC1, ENC2, ENC3, BOTT, DEC3, DEC2, DEC1, HEAD };
+
+bool make_net(const int32_t dims[3], int B, Net *n) {
+    if (B != 32) return false;  // the 32/64/128/256 network
+    for (int a = 0; a < 3; ++a)
+        if (dims[a] < 8 || dims[a] % 8 != 0 || dims[a] > 1024) return false;
+    n->B = B;
+    for (int l = 0; l < 4; ++l) {
+        n->d[l].nx = dims[0] >> l;
+        n->d[l].ny = dims[1] >> l;
+        n->d[l].nz = dims[2] >> l;
+        n->d[l].V = (int64_t)n->d[l].nx * n->d[l].ny * n->d[l].nz;
+    }
+    const int io[8][2] = {{1, B}, {B, 2 * B}, {2 * B, 4 * B}, {4 * B, 8 * B},
+                          {12 * B, 4 * B}, {6 * B, 2 * B}, {3 * B, B}, {B, 3}};
+    int64_t off = 0;
+    for (int l = 0; l < 8; ++l) {
+        Layer &L = n->L[l];
+        L.cin = io[l][0];
+        L.cout = io[l][1];
+        L.w_off = off;
+        off += (int64_t)(l == HEAD ? 1 : 27) * L.cin * L.cout;
+        L.b_off = off;
+        off += L.cout;
+    }
+    n->n_params = off;
+    return true;
+}
+
+// Buffers in the workspace (bf16 unless noted).  Concatenations:
+//   cat1 [V1][3B] = up(dec2) 2B | enc1 B;  cat2 [V2][6B] = up(dec3) 4B | enc2 2B;
+//   cat3 [V3][12B] = up(bott) 8B | enc3 4B.
+struct UWs {
+    u16 *wb[7], *wt[7];  // conv weights [27][cout][cin] and transposed/reversed
+    u16 *cat1, *cat2, *cat3, *p2, *p3, *p4, *bott, *dec3, *dec2, *dec1;
+    u16 *g_dec1, *g_cat1, *g_dec2, *g_cat2, *g_dec3, *g_cat3, *g_bott, *g_p4, *g_enc3, *g_p3, *g_enc2,
+        *g_p2, *g_enc1;
+    float *part;      // weight-gradient partials
+    int64_t part_n;   // floats in part
+    double *lpart;    // loss partials
+    size_t bytes;
+};
+
+constexpr int kLossBlocks = 1024;
+constexpr int kHeadBlocks = 512;
+constexpr int kConv1Blocks = 512;
+
+int wgrad_chunks(int64_t V) { return (int)std::max<int64_t>(1, std::min<int64_t>(64, V / 16384)); }
+
+UWs carve_unet(void *base, const Net &n) {
+    UWs w;
+    Carver c(base);
+    const int B = n.B;
+    const int64_t V1 = n.d[0].V, V2 = n.d[1].V, V3 = n.d[2].V, V4 = n.d[3].V;
+    for (int l = ENC2; l <= DEC1; ++l) {
+        const int64_t nw = 27LL * n.L[l].cin * n.L[l].cout;
+        w.wb[l] = c.take<u16>(nw);
+        w.wt[l] = c.take<u16>(nw);
+    }
+    w.wb[ENC1] = w.wt[ENC1] = nullptr;
+    w.cat1 = c.take<u16>(V1 * 3 * B);
+    w.cat2 = c.take<u16>(V2 * 6 * B);
+    w.cat3 = c.take<u16>(V3 * 12 * B);
+    w.p2 = c.take<u16>(V2 * B);
+    w.p3 = c.take<u16>(V3 * 2 * B);
+    w.p4 = c.take<u16>(V4 * 4 * B);
+    w.bott = c.take<u16>(V4 * 8 * B);
+    w.dec3 = c.take<u16>(V3 * 4 * B);
+    w.dec2 = c.take<u16>(V2 * 2 * B);
+    w.dec1 = c.take<u16>(V1 * B);
+    w.g_dec1 = c.take<u16>(V1 * B);
+    w.g_cat1 = c.take<u16>(V1 * 3 * B);
+    w.g_dec2 = c.take<u16>(V2 * 2 * B);
+    w.g_cat2 = c.take<u16>(V2 * 6 * B);
+    w.g_dec3 = c.take<u16>(V3 * 4 * B);
+    w.g_cat3 = c.take<u16>(V3 * 12 * B);
+    w.g_bott = c.take<u16>(V4 * 8 * B);
+    w.g_p4 = c.take<u16>(V4 * 4 * B);
+    w.g_enc3 = c.take<u16>(V3 * 4 * B);
+    w.g_p3 = c.take<u16>(V3 * 2 * B);
+    w.g_enc2 = c.take<u16>(V2 * 2 * B);
+    w.g_p2 = c.take<u16>(V2 * B);
+    w.g_enc1 = c.take<u16>(V1 * B);
+    int64_t pn = (int64_t)kConv1Blocks * 27 * B;
+    pn = std::max<int64_t>(pn, (int64_t)kHeadBlocks * (3 * B + 3));
+    pn = std::max<int64_t>(pn, (int64_t)kSumBlocks * 8 * B);
+    const int lev[7] = {0, 1, 2, 3, 2, 1, 0};
+    for (int l = ENC2; l <= DEC1; ++l)
+        pn = std::max<int64_t>(pn, (int64_t)wgrad_chunks(n.d[lev[l]].V) * 27 * n.L[l].cin * n.L[l].cout);
+    w.part = c.take<float>(pn);
+    w.part_n = pn;
+    w.lpart = c.take<double>(kLossBlocks);
+    w.bytes = c.off;
+    return w;
+}
+
+dgr_status check_unet(const int32_t dims[3], int B, Net *n, void *ws, size_t ws_bytes) {
+    DGR_CHECK(dims != nullptr, "dims is null");
+    DGR_CHECK(make_net(dims, B, n),
+              "U-Net needs base width 32 and extents that are multiples of 8 in [8, 1024]");
+    DGR_CHECK(ws != nullptr, "workspace is null");
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign)
+        return fail(DGR_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    const size_t need = carve_unet(nullptr, *n).bytes;
+    if (ws_bytes < need) return fail(DGR_ERR_WORKSPACE, "workspace holds %zu bytes, U-Net needs %zu", ws_bytes, need);
+    return DGR_OK;
+}
+
+dgr_status launch_conv(const u16 *x, int xs, const Vol &d, int cin, const u16 *w, const float *bias,
+                       int cout, int relu, u16 *y, int ys, hipStream_t st) {
+    const dim3 grid((unsigned)((d.V + 255) / 256), (unsigned)(cout % 64 == 0 ? cout / 64 : cout / 32));
+    if (cout % 64 == 0)
+        conv3_mfma<4><<<grid, dim3(256), 0, st>>>(x, xs, d, cin, w, bias, cout, relu, y, ys);
+    else
+        conv3_mfma<2><<<grid, dim3(256), 0, st>>>(x, xs, d, cin, w, bias, cout, relu, y, ys);
+    DGR_LAUNCH_CHECK();
+    return DGR_OK;
+}
+
+// dW (binary32 [27][cout][cin]) and db ([cout]) of one conv3 layer.
+dgr_status launch_wgrad(const u16 *x, int xs, const Vol &d, int cin, const u16 *dy, int cout, float *part,
+                        float *dW, float *db, hipStream_t st) {
+    const int nc = wgrad_chunks(d.V);
+    const int64_t chunk = (d.V + nc - 1) / nc;
+    const dim3 grid((unsigned)(27 * (cout / 32) * (cin / 32)), (unsigned)nc);
+    conv3_wgrad<<<grid, dim3(256), 0, st>>>(x, xs, d, cin, dy, cout, cout, chunk, part);
+    DGR_LAUNCH_CHECK();
+    const int64_t n = 27LL * cout * cin;
+    sum_chunks<<<blocks_for(n), 256, 0, st>>>(part, nc, n, dW);
+    DGR_LAUNCH_CHECK();
+    channel_sums<<<kSumBlocks, 256, 0, st>>>(dy, cout, cout, d.V, part);
+    DGR_LAUNCH_CHECK();
+    sum_parts<<<blocks_for(cout), 256, 0, st>>>(part, kSumBlocks, cout, db);
+    DGR_LAUNCH_CHECK();
+    return DGR_OK;
+}
+
+dgr_status up_level(const u16 *src, const Vol &fine, const Vol &coarse, int C, u16 *cat, int cs,
+                    hipStream_t st) {
+    up2_fwd<<<blocks_for(coarse.V * (C / 8)), 256, 0, st>>>(src, fine, coarse, C, cat, cs);
+    DGR_LAUNCH_CHECK();
+    return DGR_OK;
+}
+
+dgr_status pool_level(const u16 *a, int as, const Vol &fine, const Vol &coarse, int C, u16 *out,
+                      hipStream_t st) {
+    pool2_fwd<<<blocks_for(coarse.V * (C / 8)), 256, 0, st>>>(a, as, fine, coarse, C, out);
+    DGR_LAUNCH_CHECK();
+    return DGR_OK;
+}
+
+}  // namespace
+}  // namespace dgr
+
+using namespace dgr;
+
+#define DGR_RET(expr)                      \
+    do {                                   \
+        dgr_status s_ = (expr);            \
+        if (s_ != DGR_OK) return s_;       \
+    } while (0)
+
+extern "C" int64_t dgr_unet_param_count(int32_t base) {
+    const int32_t dims[3] = {8, 8, 8};
+    Net n;
+    if (!make_net(dims, base, &n)) return -1;
+    return n.n_params;
+}
+
+extern "C" size_t dgr_unet_workspace(const int32_t dims[3], int32_t base) {
+    Net n;
+    if (!dims || !make_net(dims, base, &n)) return 0;
+    return carve_unet(nullptr, n).bytes;
+}
+
+extern "C" dgr_status dgr_unet_forward(const float *params, const float *input, const int32_t dims[3],
+                                       int32_t base, float *out, void *ws, size_t ws_bytes, void *stream) {
+    Net n;
+    DGR_RET(check_unet(dims, base, &n, ws, ws_bytes));
+    DGR_CHECK(params && input && out, "null pointer argument");
+    hipStream_t st = as_stream(stream);
+    UWs w = carve_unet(ws, n);
+    const int B = n.B;
+    for (int l = ENC2; l <= DEC1; ++l) {
+        const Layer &L = n.L[l];
+        cast_weights<<<blocks_for(27LL * L.cin * L.cout), 256, 0, st>>>(params + L.w_off, L.cout, L.cin,
+                                                                         w.wb[l], w.wt[l]);
+        DGR_LAUNCH_CHECK();
+    }
+    const Vol &d1 = n.d[0], &d2 = n.d[1], &d3 = n.d[2], &d4 = n.d[3];
+    auto P = [&](int l) { return params + n.L[l].w_off; };
+    auto Bi = [&](int l) { return params + n.L[l].b_off; };
+    // encoder (encoder outputs live in the concatenation buffers' skip slices)
+    conv1_fwd<<<blocks_for(d1.V), 256, 0, st>>>(input, d1, P(ENC1), Bi(ENC1), B, w.cat1 + 2 * B, 3 * B);
+    DGR_LAUNCH_CHECK();
+    DGR_RET(pool_level(w.cat1 + 2 * B, 3 * B, d1, d2, B, w.p2, st));
+    DGR_RET(launch_conv(w.p2, B, d2, B, w.wb[ENC2], Bi(ENC2), 2 * B, 1, w.cat2 + 4 * B, 6 * B, st));
+    DGR_RET(pool_level(w.cat2 + 4 * B, 6 * B, d2, d3, 2 * B, w.p3, st));
+    DGR_RET(launch_conv(w.p3, 2 * B, d3, 2 * B, w.wb[ENC3], Bi(ENC3), 4 * B, 1, w.cat3 + 8 * B, 12 * B, st));
+    DGR_RET(pool_level(w.cat3 + 8 * B, 12 * B, d3, d4, 4 * B, w.p4, st));
+    DGR_RET(launch_conv(w.p4, 4 * B, d4, 4 * B, w.wb[BOTT], Bi(BOTT), 8 * B, 1, w.bott, 8 * B, st));
+    // decoder
+    DGR_RET(up_level(w.bott, d3, d4, 8 * B, w.cat3, 12 * B, st));
+    DGR_RET(launch_conv(w.cat3, 12 * B, d3, 12 * B, w.wb[DEC3], Bi(DEC3), 4 * B, 1, w.dec3, 4 * B, st));
+    DGR_RET(up_level(w.dec3, d2, d3, 4 * B, w.cat2, 6 * B, st));
+    DGR_RET(launch_conv(w.cat2, 6 * B, d2, 6 * B, w.wb[DEC2], Bi(DEC2), 2 * B, 1, w.dec2, 2 * B, st));
+    DGR_RET(up_level(w.dec2, d1, d2, 2 * B, w.cat1, 3 * B, st));
+    DGR_RET(launch_conv(w.cat1, 3 * B, d1, 3 * B, w.wb[DEC1], Bi(DEC1), B, 1, w.dec1, B, st));
+    head_fwd<<<blocks_for(d1.V), 256, 0, st>>>(w.dec1, B, d1.V, P(HEAD), Bi(HEAD), out);
+    DGR_LAUNCH_CHECK();
+    return DGR_OK;
+}
+
+extern "C" dgr_status dgr_unet_backward(const float *params, const float *input, const int32_t dims[3],
+                                        int32_t base, const float *dout, float *grad, void *ws,
+                                        size_t ws_bytes, void *stream) {
+    Net n;
+    DGR_RET(check_unet(dims, base, &n, ws, ws_bytes));
+    DGR_CHECK(params && input && dout && grad, "null pointer argument");
+    hipStream_t st = as_stream(stream);
+    UWs w = carve_unet(ws, n);
+    const int B = n.B;
+    const Vol &d1 = n.d[0], &d2 = n.d[1], &d3 = n.d[2], &d4 = n.d[3];
+    auto G = [&](int l) { return grad + n.L[l].w_off; };
+    auto Gb = [&](int l) { return grad + n.L[l].b_off; };
+    // head
+    head_bwd<<<kHeadBlocks, 256, 0, st>>>(w.dec1, B, d1.V, params + n.L[HEAD].w_off, dout, w.g_dec1, w.part);
+    DGR_LAUNCH_CHECK();
+    sum_parts<<<blocks_for(3 * B + 3), 256, 0, st>>>(w.part, kHeadBlocks, 3 * B + 3, G(HEAD));
+    DGR_LAUNCH_CHECK();
+    // dec1: input cat1, output grad g_dec1 (pre-activation)
+    DGR_RET(launch_wgrad(w.cat1, 3 * B, d1, 3 * B, w.g_dec1, B, w.part, G(DEC1), Gb(DEC1), st));
+    DGR_RET(launch_conv(w.g_dec1, B, d1, B, w.wt[DEC1], nullptr, 3 * B, 0, w.g_cat1, 3 * B, st));
+    up2_bwd_relu<<<blocks_for(d2.V * (2 * B / 8)), 256, 0, st>>>(w.g_cat1, 3 * B, d1, d2, 2 * B, w.dec2, w.g_dec2);
+    DGR_LAUNCH_CHECK();
+    // dec2
+    DGR_RET(launch_wgrad(w.cat2, 6 * B, d2, 6 * B, w.g_dec2, 2 * B, w.part, G(DEC2), Gb(DEC2), st));
+    DGR_RET(launch_conv(w.g_dec2, 2 * B, d2, 2 * B, w.wt[DEC2], nullptr, 6 * B, 0, w.g_cat2, 6 * B, st));
+    up2_bwd_relu<<<blocks_for(d3.V * (4 * B / 8)), 256, 0, st>>>(w.g_cat2, 6 * B, d2, d3, 4 * B, w.dec3, w.g_dec3);
+    DGR_LAUNCH_CHECK();
+    // dec3
+    DGR_RET(launch_wgrad(w.cat3, 12 * B, d3, 12 * B, w.g_dec3, 4 * B, w.part, G(DEC3), Gb(DEC3), st));
+    DGR_RET(launch_conv(w.g_dec3, 4 * B, d3, 4 * B, w.wt[DEC3], nullptr, 12 * B, 0, w.g_cat3, 12 * B, st));
+    up2_bwd_relu<<<blocks_for(d4.V * (8 * B / 8)), 256, 0, st>>>(w.g_cat3, 12 * B, d3, d4, 8 * B, w.bott, w.g_bott);
+    DGR_LAUNCH_CHECK();
+    // bottleneck: input p4
+    DGR_RET(launch_wgrad(w.p4, 4 * B, d4, 4 * B, w.g_bott, 8 * B, w.part, G(BOTT), Gb(BOTT), st));
+    DGR_RET(launch_conv(w.g_bott, 8 * B, d4, 8 * B, w.wt[BOTT], nullptr, 4 * B, 0, w.g_p4, 4 * B, st));
+    // enc3: its output feeds cat3 (skip) and pool -> bott
+    skip_bwd_relu<<<blocks_for(d3.V * (4 * B / 8)), 256, 0, st>>>(w.g_cat3 + 8 * B, 12 * B, w.g_p4, d3, d4,
+                                                                   4 * B, w.cat3 + 8 * B, 12 * B, w.g_enc3);
+    DGR_LAUNCH_CHECK();
+    DGR_RET(launch_wgrad(w.p3, 2 * B, d3, 2 * B, w.g_enc3, 4 * B, w.part, G(ENC3), Gb(ENC3), st));
+    DGR_RET(launch_conv(w.g_enc3, 4 * B, d3, 4 * B, w.wt[ENC3], nullptr, 2 * B, 0, w.g_p3, 2 * B, st));
+    // enc2
+    skip_bwd_relu<<<blocks_for(d2.V * (2 * B / 8)), 256, 0, st>>>(w.g_cat2 + 4 * B, 6 * B, w.g_p3, d2, d3,
+                                                                   2 * B, w.cat2 + 4 * B, 6 * B, w.g_enc2);
+    DGR_LAUNCH_CHECK();
+    DGR_RET(launch_wgrad(w.p2, B, d2, B, w.g_enc2, 2 * B, w.part, G(ENC2), Gb(ENC2), st));
+    DGR_RET(launch_conv(w.g_enc2, 2 * B, d2, 2 * B, w.wt[ENC2], nullptr, B, 0, w.g_p2, B, st));
+    // enc1 (first layer, VALU)
+    skip_bwd_relu<<<blocks_for(d1.V * (B / 8)), 256, 0, st>>>(w.g_cat1 + 2 * B, 3 * B, w.g_p2, d1, d2, B,
+                                                               w.cat1 + 2 * B, 3 * B, w.g_enc1);
+    DGR_LAUNCH_CHECK();
+    conv1_wgrad<<<kConv1Blocks, 256, 0, st>>>(input, d1, w.g_enc1, B, B, w.part);
+    DGR_LAUNCH_CHECK();
+    sum_parts<<<blocks_for(27 * B), 256, 0, st>>>(w.part, kConv1Blocks, 27 * B, G(ENC1));
+    DGR_LAUNCH_CHECK();
+    channel_sums<<<kSumBlocks, 256, 0, st>>>(w.g_enc1, B, B, d1.V, w.part);
+    DGR_LAUNCH_CHECK();
+    sum_parts<<<blocks_for(B), 256, 0, st>>>(w.part, kSumBlocks, B, Gb(ENC1));
+    DGR_LAUNCH_CHECK();
+    return DGR_OK;
+}
+
+extern "C" size_t dgr_unet_loss_workspace(void) { return align_up(sizeof(double) * kLossBlocks); }
+
+extern "C" dgr_status dgr_unet_loss(const float *out, const float *target, int64_t n_voxels, float *loss,
+                                    float *dout, void *ws, size_t ws_bytes, void *stream) {
+    DGR_CHECK(n_voxels >= 1, "n_voxels must be >= 1");
+    DGR_CHECK(out && target && loss && dout && ws, "null pointer argument");
+    if (ws_bytes < dgr_unet_loss_workspace()) return fail(DGR_ERR_WORKSPACE, "workspace too small");
+    hipStream_t st = as_stream(stream);
+    double *part = static_cast<double *>(ws);
+    const int nb = (int)std::min<int64_t>(kLossBlocks, (n_voxels + 255) / 256);
+    loss_kernel<<<nb, 256, 0, st>>>(out, target, n_voxels, dout, part);
+    DGR_LAUNCH_CHECK();
+    loss_final<<<1, 256, 0, st>>>(part, nb, n_voxels, loss);
+    DGR_LAUNCH_CHECK();
+    return DGR_OK;
+}
+
+// ---- single layers, for tests -----------------------------------------------------------------
+extern "C" dgr_status dgr_conv3_forward(const uint16_t *x, int32_t x_stride, const int32_t dims[3],
+                                        int32_t cin, const uint16_t *w, const float *bias, int32_t cout,
+                                        int32_t relu, uint16_t *y, int32_t y_stride, void *stream) {
+    DGR_CHECK(x && w && y && dims, "null pointer argument");
+    DGR_CHECK(cin >= 32 && cin % 32 == 0 && cout >= 32 && cout % 32 == 0, "cin and cout must be multiples of 32");
+    DGR_CHECK(x_stride >= cin && x_stride % 8 == 0 && y_stride >= cout && y_stride % 8 == 0,
+              "strides must cover the channels and be multiples of 8");
+    DGR_CHECK(((uintptr_t)x | (uintptr_t)w | (uintptr_t)y) % 16 == 0, "pointers must be 16-byte aligned");
+    Vol d{dims[0], dims[1], dims[2], (int64_t)dims[0] * dims[1] * dims[2]};
+    DGR_CHECK(dims[0] >= 1 && dims[1] >= 1 && dims[2] >= 1, "dims must be >= 1");
+    return launch_conv(reinterpret_cast<const u16 *>(x), x_stride, d, cin, reinterpret_cast<const u16 *>(w),
+                       bias, cout, relu, reinterpret_cast<u16 *>(y), y_stride, as_stream(stream));
+}
+
+extern "C" size_t dgr_conv3_grad_workspace(const int32_t dims[3], int32_t cin, int32_t cout) {
+    if (!dims || cin < 1 || cout < 1) return 0;
+    const int64_t V = (int64_t)dims[0] * dims[1] * dims[2];
+    const int64_t pn = std::max<int64_t>((int64_t)wgrad_chunks(V) * 27 * cin * cout, (int64_t)kSumBlocks * cout);
+    return align_up(sizeof(float) * pn) + 2 * align_up(sizeof(u16) * 27 * cin * cout);
+}
+
+extern "C" dgr_status dgr_conv3_backward(const uint16_t *x, int32_t x_stride, const int32_t dims[3],
+                                         int32_t cin, const float *w, const uint16_t *dy, int32_t cout,
+                                         float *dw, float *db, uint16_t *dx, void *ws, size_t ws_bytes,
+                                         void *stream) {
+    DGR_CHECK(x && w && dy && dw && db && dx && dims && ws, "null pointer argument");
+    DGR_CHECK(cin >= 32 && cin % 32 == 0 && cout >= 32 && cout % 32 == 0, "cin and cout must be multiples of 32");
+    DGR_CHECK(x_stride >= cin && x_stride % 8 == 0, "x stride must cover cin and be a multiple of 8");
+    DGR_CHECK(((uintptr_t)x | (uintptr_t)dy | (uintptr_t)dx) % 16 == 0, "pointers must be 16-byte aligned");
+    DGR_CHECK(dims[0] >= 1 && dims[1] >= 1 && dims[2] >= 1, "dims must be >= 1");
+    if (ws_bytes < dgr_conv3_grad_workspace(dims, cin, cout)) return fail(DGR_ERR_WORKSPACE, "workspace too small");
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign) return fail(DGR_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    hipStream_t st = as_stream(stream);
+    Vol d{dims[0], dims[1], dims[2], (int64_t)dims[0] * dims[1] * dims[2]};
+    const int64_t V = d.V;
+    Carver c(ws);
+    float *part = c.take<float>(std::max<int64_t>((int64_t)wgrad_chunks(V) * 27 * cin * cout, (int64_t)kSumBlocks * cout));
+    u16 *wb = c.take<u16>(27LL * cin * cout);
+    u16 *wt = c.take<u16>(27LL * cin * cout);
+    cast_weights<<<blocks_for(27LL * cin * cout), 256, 0, st>>>(w, cout, cin, wb, wt);
+    DGR_LAUNCH_CHECK();
+    DGR_RET(launch_wgrad(reinterpret_cast<const u16 *>(x), x_stride, d, cin, reinterpret_cast<const u16 *>(dy),
+                         cout, part, dw, db, st));
+    return launch_conv(reinterpret_cast<const u16 *>(dy), cout, d, cout, wt, nullptr, cin, 0,
+                       reinterpret_cast<u16 *>(dx), cin, st);
+}

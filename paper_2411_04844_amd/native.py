@@ -70,13 +70,24 @@ _SIGS = {
     "dgr_init_from_volume": ("st", ["p", "grid", "f32", "i64", "p", "f32", "p", "p", "p", "p", "p",
                                     "sz", "p"]),
     "dgr_fit_density_scale": ("st", ["p", "p", "i64", "p", "i64", "p", "p", "sz", "p"]),
+    "dgr_unet_param_count": (ctypes.c_int64, ["i32"]),
+    "dgr_unet_workspace": (ctypes.c_size_t, ["dims", "i32"]),
+    "dgr_unet_forward": ("st", ["p", "p", "dims", "i32", "p", "p", "sz", "p"]),
+    "dgr_unet_backward": ("st", ["p", "p", "dims", "i32", "p", "p", "p", "sz", "p"]),
+    "dgr_unet_loss_workspace": (ctypes.c_size_t, []),
+    "dgr_unet_loss": ("st", ["p", "p", "i64", "p", "p", "p", "sz", "p"]),
+    "dgr_conv3_forward": ("st", ["p", "i32", "dims", "i32", "p", "p", "i32", "i32", "p", "i32", "p"]),
+    "dgr_conv3_grad_workspace": (ctypes.c_size_t, ["dims", "i32", "i32"]),
+    "dgr_conv3_backward": ("st", ["p", "i32", "dims", "i32", "p", "p", "i32", "p", "p", "p", "p", "sz",
+                                  "p"]),
     "dgr_status_string": (ctypes.c_char_p, ["i32"]),
     "dgr_last_error": (ctypes.c_char_p, []),
     "dgr_version": (ctypes.c_int32, []),
 }
 _CT = {"p": ctypes.c_void_p, "i64": ctypes.c_int64, "i32": ctypes.c_int32, "f32": ctypes.c_float,
        "sz": ctypes.c_size_t, "grid": ctypes.POINTER(DgrGrid), "trunc": ctypes.POINTER(DgrTrunc),
-       "geom": ctypes.POINTER(DgrGeometry), "st": ctypes.c_int}
+       "geom": ctypes.POINTER(DgrGeometry), "st": ctypes.c_int,
+       "dims": ctypes.POINTER(ctypes.c_int32)}
 
 
 def lib():
@@ -392,3 +403,99 @@ def dgr_fit_density_scale(p1, target, density, kappa=None, ws: Workspace | None 
         _ptr(p1), _ptr(target), p1.numel(), _ptr(density), density.numel(), _ptr(kappa), p, sz,
         _stream()))
     return kappa
+
+
+# ---- learned initialisation (U-Net) -----------------------------------------------
+UNET_BASE = 32
+
+
+def _dims(shape3):
+    """Volume shape (nz, ny, nx) -> C dims {nx, ny, nz}."""
+    nz, ny, nx = (int(v) for v in shape3)
+    return (ctypes.c_int32 * 3)(nx, ny, nz)
+
+
+def dgr_unet_param_count(base=UNET_BASE) -> int:
+    n = int(lib().dgr_unet_param_count(base))
+    if n < 0:
+        raise ValueError(f"unsupported U-Net base width {base}")
+    return n
+
+
+def dgr_unet_forward(params, x, out=None, ws: Workspace | None = None, base=UNET_BASE):
+    """x float32 [nz, ny, nx] -> out float32 [nz, ny, nx, 3]; ws keeps the
+    activations for dgr_unet_backward."""
+    _need(params, torch.float32, (dgr_unet_param_count(base),), "params")
+    _need(x, torch.float32, None, "x")
+    if out is None:
+        out = torch.empty(tuple(x.shape) + (3,), dtype=torch.float32, device=x.device)
+    _need(out, torch.float32, tuple(x.shape) + (3,), "out")
+    dims = _dims(x.shape)
+    need = int(lib().dgr_unet_workspace(dims, base))
+    if need == 0:
+        raise ValueError(f"unsupported U-Net volume shape {tuple(x.shape)}")
+    ws = ws or Workspace(x.device)
+    p, sz = ws.ptr_size(need)
+    _check("dgr_unet_forward", lib().dgr_unet_forward(_ptr(params), _ptr(x), dims, base, _ptr(out), p,
+                                                      sz, _stream()))
+    return out
+
+
+def dgr_unet_backward(params, x, dout, ws: Workspace, grad=None, base=UNET_BASE):
+    _need(dout, torch.float32, tuple(x.shape) + (3,), "dout")
+    if grad is None:
+        grad = torch.empty_like(params)
+    _need(grad, torch.float32, tuple(params.shape), "grad")
+    dims = _dims(x.shape)
+    p, sz = ws.ptr_size(int(lib().dgr_unet_workspace(dims, base)))
+    _check("dgr_unet_backward", lib().dgr_unet_backward(_ptr(params), _ptr(x), dims, base, _ptr(dout),
+                                                        _ptr(grad), p, sz, _stream()))
+    return grad
+
+
+def dgr_unet_loss(out, target, loss=None, dout=None, ws: Workspace | None = None):
+    _need(out, torch.float32, None, "out")
+    _need(target, torch.float32, tuple(out.shape), "target")
+    if loss is None:
+        loss = torch.empty((), dtype=torch.float32, device=out.device)
+    if dout is None:
+        dout = torch.empty_like(out)
+    ws = ws or Workspace(out.device)
+    p, sz = ws.ptr_size(int(lib().dgr_unet_loss_workspace()))
+    _check("dgr_unet_loss", lib().dgr_unet_loss(_ptr(out), _ptr(target), out.numel() // 3, _ptr(loss),
+                                                _ptr(dout), p, sz, _stream()))
+    return loss, dout
+
+
+def dgr_conv3_forward(x, cin, w, bias, cout, relu=True, y=None, y_stride=None):
+    """x bfloat16 [nz, ny, nx, x_stride]; w bfloat16 [27, cout, cin]."""
+    _need(x, torch.bfloat16, None, "x")
+    _need(w, torch.bfloat16, (27, cout, cin), "w")
+    if bias is not None:
+        _need(bias, torch.float32, (cout,), "bias")
+    ys = y_stride or cout
+    if y is None:
+        y = torch.zeros(tuple(x.shape[:3]) + (ys,), dtype=torch.bfloat16, device=x.device)
+    _check("dgr_conv3_forward", lib().dgr_conv3_forward(_ptr(x), x.shape[3], _dims(x.shape[:3]), cin,
+                                                        _ptr(w), _ptr(bias), cout, int(relu), _ptr(y),
+                                                        y.shape[3], _stream()))
+    return y
+
+
+def dgr_conv3_backward(x, cin, w, dy, ws: Workspace | None = None):
+    """-> (dw float32 [27, cout, cin], db float32 [cout], dx bfloat16 [..., cin])."""
+    _need(x, torch.bfloat16, None, "x")
+    cout = w.shape[1]
+    _need(w, torch.float32, (27, cout, cin), "w")
+    _need(dy, torch.bfloat16, tuple(x.shape[:3]) + (cout,), "dy")
+    dev = x.device
+    dw = torch.empty((27, cout, cin), dtype=torch.float32, device=dev)
+    db = torch.empty(cout, dtype=torch.float32, device=dev)
+    dx = torch.empty(tuple(x.shape[:3]) + (cin,), dtype=torch.bfloat16, device=dev)
+    dims = _dims(x.shape[:3])
+    ws = ws or Workspace(dev)
+    p, sz = ws.ptr_size(int(lib().dgr_conv3_grad_workspace(dims, cin, cout)))
+    _check("dgr_conv3_backward", lib().dgr_conv3_backward(_ptr(x), x.shape[3], dims, cin, _ptr(w), _ptr(dy),
+                                                          cout, _ptr(dw), _ptr(db), _ptr(dx), p, sz,
+                                                          _stream()))
+    return dw, db, dx
