@@ -248,6 +248,31 @@ size_t dgr_unet_loss_workspace(void);
 dgr_status dgr_unet_loss(const float *out, const float *target, int64_t n_voxels, float *loss,
                          float *dout, void *ws, size_t ws_bytes, void *stream);
 
+/* 2x2x2 mean of a binary32 volume [nz][ny][nx] (dims even) into
+ * [nz/2][ny/2][nx/2]: the network is trained at twice the voxel size of the
+ * reconstruction grid and reads the pooled FDK volume. */
+dgr_status dgr_pool2_f32(const float *in, const int32_t dims[3], float *out, void *stream);
+
+/* Training targets on `grid` from a converged Gaussian set (mu, scale [n][3])
+ * and its voxelization `volume`: target[v] = (volume[v] / input_scale,
+ * mean over the Gaussians whose mean lies in v of log(geometric-mean scale in
+ * voxels) or 0, 1 if there is such a Gaussian else 0).  Sums are fixed point
+ * (deterministic). */
+size_t dgr_unet_targets_workspace(const dgr_grid *grid);
+dgr_status dgr_unet_targets(const float *mu, const float *scale, int64_t n, const dgr_grid *grid,
+                            const float *volume, float input_scale, float *target, void *ws,
+                            size_t ws_bytes, void *stream);
+
+/* Initial Gaussians drawn from the network's output out [V][3] on `grid`:
+ * voxel weight sigmoid(o_o), drawn with replacement by inverse CDF as in
+ * dgr_init_from_volume (uniforms [n][4]), mean = voxel centre +
+ * (uniforms[i][1..3] - 1/2) voxel, isotropic scale exp(o_s) voxels clamped
+ * to [0.25, 8], identity rotation, density max(o_d, 0) * input_scale. */
+size_t dgr_init_from_unet_workspace(const dgr_grid *grid);
+dgr_status dgr_init_from_unet(const float *out, const dgr_grid *grid, int64_t n,
+                              const float *uniforms, float input_scale, float *mu, float *scale,
+                              float *quat, float *density, void *ws, size_t ws_bytes, void *stream);
+
 /* One conv3 layer on the matrix cores (the network's building block).
  * x: bfloat16 [nz][ny][nx][x_stride] (channels 0..cin-1 read); w: bfloat16
  * [27][cout][cin]; bias: binary32 [cout] or NULL; y: bfloat16

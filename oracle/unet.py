@@ -213,3 +213,46 @@ def conv3_brute(x, W, b):
                                 acc += W[t, o, i] * x[zz, y2, x2, i]
                     y[z, yy, xx, o] = acc
     return y
+
+
+# ---- around the network: training targets and the proposed Gaussians -----------------
+def targets(mu, scale, dims, lo, inv_h, volume, input_scale):
+    """target [nz, ny, nx, 3] = (volume / input_scale, mean log geometric-mean
+    scale in voxels of the Gaussians whose mean lies in the voxel (else 0),
+    1 if there is one else 0).  dims = (nx, ny, nz)."""
+    nx, ny, nz = dims
+    cnt = np.zeros(nz * ny * nx)
+    lsum = np.zeros(nz * ny * nx)
+    for m, s in zip(np.asarray(mu, np.float64), np.asarray(scale, np.float64)):
+        u = (m - np.asarray(lo, np.float64)) * np.asarray(inv_h, np.float64)
+        if np.all(u >= 0) and u[0] < nx and u[1] < ny and u[2] < nz:
+            i = np.floor(u).astype(int)
+            v = (i[2] * ny + i[1]) * nx + i[0]
+            cnt[v] += 1
+            lsum[v] += np.mean(np.log(s * np.asarray(inv_h, np.float64)))
+    t = np.zeros((nz * ny * nx, 3))
+    t[:, 0] = np.asarray(volume, np.float64).ravel() / input_scale
+    has = cnt > 0
+    t[has, 1] = lsum[has] / cnt[has]
+    t[:, 2] = has
+    return t.reshape(nz, ny, nx, 3)
+
+
+def draw_from_fields(out, dims, lo, inv_h, uniforms, input_scale):
+    """Gaussians drawn from network output out [nz, ny, nx, 3]: voxel v with
+    probability sigmoid(o_o[v]) / sum (inverse CDF of uniforms[:, 0], first v
+    whose cumulative weight exceeds u W), mean = centre + (u_1..3 - 1/2) voxel,
+    isotropic scale clip(exp(o_s), 1/4, 8) voxels, density max(o_d, 0) s_in."""
+    nx, ny, nz = dims
+    o = np.asarray(out, np.float64).reshape(-1, 3)
+    w = 1.0 / (1.0 + np.exp(-o[:, 2]))
+    cdf = np.cumsum(w)
+    U = np.asarray(uniforms, np.float64)
+    v = np.searchsorted(cdf, U[:, 0] * cdf[-1], side="right")
+    idx = np.stack([v % nx, (v // nx) % ny, v // (nx * ny)], axis=1)
+    lo, ih = np.asarray(lo, np.float64), np.asarray(inv_h, np.float64)
+    mu = lo + (idx + 0.5 + (U[:, 1:4] - 0.5)) / ih
+    s_vox = np.clip(np.exp(o[v, 1]), 0.25, 8.0)
+    sc = s_vox[:, None] / ih
+    rho = np.maximum(o[v, 0], 0.0) * input_scale
+    return mu, sc, rho, v

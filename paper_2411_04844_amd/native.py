@@ -80,6 +80,11 @@ _SIGS = {
     "dgr_conv3_grad_workspace": (ctypes.c_size_t, ["dims", "i32", "i32"]),
     "dgr_conv3_backward": ("st", ["p", "i32", "dims", "i32", "p", "p", "i32", "p", "p", "p", "p", "sz",
                                   "p"]),
+    "dgr_pool2_f32": ("st", ["p", "dims", "p", "p"]),
+    "dgr_unet_targets_workspace": (ctypes.c_size_t, ["grid"]),
+    "dgr_unet_targets": ("st", ["p", "p", "i64", "grid", "p", "f32", "p", "p", "sz", "p"]),
+    "dgr_init_from_unet_workspace": (ctypes.c_size_t, ["grid"]),
+    "dgr_init_from_unet": ("st", ["p", "grid", "i64", "p", "f32", "p", "p", "p", "p", "p", "sz", "p"]),
     "dgr_status_string": (ctypes.c_char_p, ["i32"]),
     "dgr_last_error": (ctypes.c_char_p, []),
     "dgr_version": (ctypes.c_int32, []),
@@ -499,3 +504,44 @@ def dgr_conv3_backward(x, cin, w, dy, ws: Workspace | None = None):
                                                           cout, _ptr(dw), _ptr(db), _ptr(dx), p, sz,
                                                           _stream()))
     return dw, db, dx
+
+
+def dgr_pool2_f32(x, out=None):
+    """x float32 [nz, ny, nx] (even) -> [nz/2, ny/2, nx/2] block means."""
+    _need(x, torch.float32, None, "x")
+    shp = tuple(v // 2 for v in x.shape)
+    if out is None:
+        out = torch.empty(shp, dtype=torch.float32, device=x.device)
+    _need(out, torch.float32, shp, "out")
+    _check("dgr_pool2_f32", lib().dgr_pool2_f32(_ptr(x), _dims(x.shape), _ptr(out), _stream()))
+    return out
+
+
+def dgr_unet_targets(mu, scale, grid: GridSpec, volume, input_scale, target=None, ws=None):
+    _need(volume, torch.float32, grid.shape, "volume")
+    if target is None:
+        target = torch.empty(tuple(grid.shape) + (3,), dtype=torch.float32, device=volume.device)
+    g = c_grid(grid)
+    ws = ws or Workspace(volume.device)
+    p, sz = ws.ptr_size(int(lib().dgr_unet_targets_workspace(ctypes.byref(g))))
+    _check("dgr_unet_targets", lib().dgr_unet_targets(_ptr(mu), _ptr(scale), mu.shape[0], ctypes.byref(g),
+                                                      _ptr(volume), float(input_scale), _ptr(target), p,
+                                                      sz, _stream()))
+    return target
+
+
+def dgr_init_from_unet(out, grid: GridSpec, n, uniforms, input_scale, ws=None):
+    _need(out, torch.float32, tuple(grid.shape) + (3,), "out")
+    _need(uniforms, torch.float32, (n, 4), "uniforms")
+    dev = out.device
+    mu = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    sc = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    q = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    rho = torch.empty(n, dtype=torch.float32, device=dev)
+    g = c_grid(grid)
+    ws = ws or Workspace(dev)
+    p, sz = ws.ptr_size(int(lib().dgr_init_from_unet_workspace(ctypes.byref(g))))
+    _check("dgr_init_from_unet", lib().dgr_init_from_unet(_ptr(out), ctypes.byref(g), n, _ptr(uniforms),
+                                                          float(input_scale), _ptr(mu), _ptr(sc), _ptr(q),
+                                                          _ptr(rho), p, sz, _stream()))
+    return mu, sc, q, rho

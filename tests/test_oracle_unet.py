@@ -110,3 +110,33 @@ def test_loss_value_and_gradient():
     # closed form: all-zero outputs and targets give log 2 (cross-entropy at p = 1/2)
     z = np.zeros((2, 2, 2))
     assert abs(U.loss(np.zeros((2, 2, 2, 3)), z, z, z)[0] - np.log(2.0)) < 1e-15
+
+
+def test_targets_hand_example():
+    # 2 x 2 x 2 grid on [0, 2]^3 (unit voxels); two Gaussians in voxel (1, 0, 0),
+    # one in voxel (0, 1, 1), one outside
+    dims, lo, ih = (2, 2, 2), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0)
+    mu = np.array([[1.2, 0.5, 0.1], [1.9, 0.2, 0.7], [0.5, 1.5, 1.5], [2.5, 0.5, 0.5]])
+    sc = np.array([[1.0, 1.0, 1.0], [2.0, 2.0, 2.0], [1.0, 2.0, 4.0], [1.0, 1.0, 1.0]])
+    vol = np.arange(8.0).reshape(2, 2, 2)
+    t = U.targets(mu, sc, dims, lo, ih, vol, 0.5)
+    np.testing.assert_allclose(t[..., 0], vol / 0.5)
+    assert t[0, 0, 1, 2] == 1 and t[1, 1, 0, 2] == 1 and t[..., 2].sum() == 2
+    assert abs(t[0, 0, 1, 1] - 0.5 * np.log(2.0)) < 1e-15     # mean of log 1 and log 2
+    assert abs(t[1, 1, 0, 1] - np.log(2.0)) < 1e-15           # log of (1 * 2 * 4)^(1/3)
+
+
+def test_draw_from_fields_frequencies_and_values():
+    # two voxels with occupancy logits giving weights 1/4 and 3/4
+    out = np.zeros((1, 1, 2, 3))
+    out[0, 0, 0] = (0.3, np.log(2.0), -np.log(3.0))   # sigmoid = 1/4
+    out[0, 0, 1] = (-1.0, 10.0, np.log(3.0))          # sigmoid = 3/4, scale clipped to 8
+    r = rng(8)
+    n = 200000
+    uni = r.uniform(size=(n, 4))
+    mu, sc, rho, v = U.draw_from_fields(out, (2, 1, 1), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), uni, 0.05)
+    frac = np.mean(v == 0)
+    assert abs(frac - 0.25) < 4 * np.sqrt(0.25 * 0.75 / n)
+    assert np.all(sc[v == 0] == 2.0) and np.all(sc[v == 1] == 8.0)
+    assert np.allclose(rho[v == 0], 0.3 * 0.05) and np.all(rho[v == 1] == 0.0)
+    assert np.all(np.floor(mu[:, 0]) == v) and np.all((mu[:, 1:] >= 0) & (mu[:, 1:] < 1))
