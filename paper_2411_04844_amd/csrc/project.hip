@@ -34,8 +34,6 @@ namespace dgr {
 namespace {
 
 constexpr int kPad = 2;
-constexpr int kTileU = 64;  // forward work-group: 64 x 4 detector pixels, one row per wave
-constexpr int kTileV = 4;
 constexpr int kXcd = 8;     // MI355X: work-groups are dealt round-robin to 8 XCDs
 constexpr int kB = 16;        // brick edge in cells (backward)
 constexpr int kBT = kB + 1;   // brick tile edge in voxels
@@ -74,23 +72,19 @@ inline Bricks bricks_of(const dgr_grid *g) {
     return b;
 }
 
-// Two zero-bordered copies: [z][y][x] (x fastest) and [z][x][y] (y fastest).
-// A view reads the copy whose fastest axis follows the detector's u axis, so
-// the 64 lanes of a wave (64 adjacent pixels of a detector row) walk along
-// contiguous memory whatever the view angle.
+// Zero-bordered copy of V, [z][y][x], two voxels of zeros on every side, so
+// the eight taps of any sample in the support need no bounds test.
 __global__ __launch_bounds__(256) void pad_volume(const float *__restrict__ V, DevGrid g, PadDims p,
-                                                  float *__restrict__ out, float *__restrict__ outT) {
+                                                  float *__restrict__ out) {
     const int64_t total = p.plane * p.pz;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
         int64_t z = i / p.plane, rem = i - z * p.plane;
         int64_t y = rem / p.px, x = rem - y * p.px;
-        const int64_t iT = (z * p.px + x) * p.py + y;
-        x -= kPad; y -= kPad; z -= kPad;
-        float v = 0.0f;
-        if (x >= 0 && y >= 0 && z >= 0 && x < g.nx && y < g.ny && z < g.nz)
-            v = V[(z * g.ny + y) * g.nx + x];
-        out[i] = v;
-        outT[iT] = v;
+        x -= kPad;
+        y -= kPad;
+        z -= kPad;
+        out[i] = (x >= 0 && y >= 0 && z >= 0 && x < g.nx && y < g.ny && z < g.nz)
+                     ? V[(z * g.ny + y) * g.nx + x] : 0.0f;
     }
 }
 
@@ -219,52 +213,38 @@ __device__ __forceinline__ bool support_range(const Ray &r, const DevGrid &g, in
     return k_interval(r, lo, hi, k0, k1);
 }
 
-typedef float f2u __attribute__((ext_vector_type(2), aligned(4)));
-
-__device__ __forceinline__ f2u ld2(const float *p) { return *reinterpret_cast<const f2u *>(p); }
-
 // Every sample of the support range has its floor in [0, dims + 2] (padded),
 // because the fixed-point position is within 2^-10 voxel of the binary64 one
 // that defined the range; its eight taps are therefore inside the padded copy.
 
-// SWAP = 0 reads the [z][y][x] copy, SWAP = 1 the [z][x][y] copy.  The wave
-// steps through the common range [kw0, kw1] of its lanes' samples, so at every
-// step its 64 rays (adjacent pixels of a detector row) sit at the same depth
-// and their taps share cache lines; a lane reads only its own range [k0, k1].
-template <int SWAP>
-__device__ float march(const float *__restrict__ vp, const PadDims &p, const Ray &r, int k0, int k1,
-                       int kw0, int kw1) {
-    const int fa = SWAP ? 1 : 0, ma = SWAP ? 0 : 1;  // fastest and middle axes
-    const int row = SWAP ? p.py : p.px;              // stride of the middle axis
-    const int mid = SWAP ? p.px : p.py;              // extent of the middle axis
-    const int plane = (int)p.plane;
-    long long uf = r.U[fa] + (long long)kw0 * r.DU[fa];
-    long long um = r.U[ma] + (long long)kw0 * r.DU[ma];
-    long long uz = r.U[2] + (long long)kw0 * r.DU[2];
-    const long long df = r.DU[fa], dm = r.DU[ma], dz = r.DU[2];
-    float acc = 0.0f;
-    for (int k = kw0; k <= kw1; ++k) {
-        if (k >= k0 && k <= k1) {
-            const int i_f = (int)(uf >> 32), i_m = (int)(um >> 32), iz = (int)(uz >> 32);
-            const float wf = (float)(unsigned)uf * kInv32;
-            const float wm = (float)(unsigned)um * kInv32;
-            const float wz = (float)(unsigned)uz * kInv32;
-            const int idx = (iz * mid + i_m) * row + i_f;
-            const f2u a00 = ld2(vp + idx), a10 = ld2(vp + idx + row);
-            const f2u a01 = ld2(vp + idx + plane), a11 = ld2(vp + idx + plane + row);
-            const float c00 = fmaf(wf, a00.y - a00.x, a00.x);
-            const float c10 = fmaf(wf, a10.y - a10.x, a10.x);
-            const float c01 = fmaf(wf, a01.y - a01.x, a01.x);
-            const float c11 = fmaf(wf, a11.y - a11.x, a11.x);
-            const float c0 = fmaf(wm, c10 - c00, c00);
-            const float c1 = fmaf(wm, c11 - c01, c01);
-            acc += fmaf(wz, c1 - c0, c0);
-        }
-        uf += df;
-        um += dm;
-        uz += dz;
+// Trilinear value of one sample from 8 taps at q (x fastest; strides sy, sz).
+__device__ __forceinline__ float trilinear(const float *q, int sy, int sz, float wx, float wy, float wz) {
+    const float c00 = fmaf(wx, q[1] - q[0], q[0]);
+    const float c10 = fmaf(wx, q[sy + 1] - q[sy], q[sy]);
+    const float c01 = fmaf(wx, q[sz + 1] - q[sz], q[sz]);
+    const float c11 = fmaf(wx, q[sz + sy + 1] - q[sz + sy], q[sz + sy]);
+    const float c0 = fmaf(wy, c10 - c00, c00);
+    const float c1 = fmaf(wy, c11 - c01, c01);
+    return fmaf(wz, c1 - c0, c0);
+}
+
+// Samples a..e of ray r, taps read from a volume whose element (0, 0, 0) is
+// the padded voxel o (strides sy, sz): the LDS box or the padded copy itself.
+__device__ __forceinline__ void march_span(const float *vol, int sy, int sz, const int o[3], const Ray &r,
+                                           int a, int e, float &acc) {
+    long long ux = r.U[0] + (long long)a * r.DU[0] - ((long long)o[0] << 32);
+    long long uy = r.U[1] + (long long)a * r.DU[1] - ((long long)o[1] << 32);
+    long long uz = r.U[2] + (long long)a * r.DU[2] - ((long long)o[2] << 32);
+    for (int k = a; k <= e; ++k) {
+        const int lx = (int)(ux >> 32), ly = (int)(uy >> 32), lz = (int)(uz >> 32);
+        const float wx = (float)(unsigned)ux * kInv32;
+        const float wy = (float)(unsigned)uy * kInv32;
+        const float wz = (float)(unsigned)uz * kInv32;
+        acc += trilinear(vol + (int64_t)lz * sz + (int64_t)ly * sy + lx, sy, sz, wx, wy, wz);
+        ux += r.DU[0];
+        uy += r.DU[1];
+        uz += r.DU[2];
     }
-    return acc;
 }
 
 __device__ __forceinline__ int wave_min(int v) {
@@ -285,31 +265,56 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
-// mode 0: write P_hat; mode 1: fused L1 (loss partial per work-group + dproj).
-// Work-groups are numbered so that each XCD (which receives every 8th
-// dispatched work-group) runs a contiguous range of tiles: neighbouring
-// detector rows of the same view share that XCD's L2.
+// Forward projection, one work-group per 16 x 16 pixel bundle of one view.
+// The bundle's rays are marched in chunks of kFwdChunk samples: for each chunk
+// the work-group finds the box of cells its samples touch (sample positions
+// are affine in k, so the floors at the two ends of each ray's span bound
+// them), copies that box of the padded volume into LDS with coalesced rows,
+// and reads the eight taps of every sample from LDS.  Rays of a bundle are
+// nearly parallel, so the box stays small (about 16 x 16 x 13 voxels for an
+// 8-voxel chunk at 45 degrees); a chunk whose box exceeds the LDS box reads
+// its taps from the padded copy instead.  Work-groups are numbered so each
+// XCD (which receives every 8th dispatched work-group) runs a contiguous range
+// of bundles.  mode 0: write P_hat; mode 1: fused L1 (loss partial per
+// work-group + dproj).
+constexpr int kBun = 16;                     // bundle edge (pixels)
+constexpr int kLX = 20, kLY = 20, kLZ = 14;  // LDS box (voxels, 22 KB)
+constexpr int kFwdChunk = 16;                // samples per chunk
+
+__device__ __forceinline__ void block_bounds(int v[6], int (*red)[8], int wave, int lane) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) v[i] = wave_min(v[i]);
+#pragma unroll
+    for (int i = 3; i < 6; ++i) v[i] = wave_max(v[i]);
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < 6; ++i) red[wave][i] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 3; ++i) v[i] = min(min(red[0][i], red[1][i]), min(red[2][i], red[3][i]));
+#pragma unroll
+    for (int i = 3; i < 6; ++i) v[i] = max(max(red[0][i], red[1][i]), max(red[2][i], red[3][i]));
+}
+
 template <int MODE>
-__global__ __launch_bounds__(256) void project_rays(const float *__restrict__ vp,
-                                                    const float *__restrict__ vpT, PadDims p, DevGrid g,
-                                                    GeomDev G, int tiles_u, int tiles_v, int64_t nb,
-                                                    const float *__restrict__ target,
-                                                    float *__restrict__ out, float inv_m,
-                                                    float *__restrict__ partial) {
+__global__ __launch_bounds__(256) void project_bundles(const float *__restrict__ vp, PadDims p, DevGrid g,
+                                                       GeomDev G, int tiles_u, int tiles_v, int64_t nb,
+                                                       const float *__restrict__ target,
+                                                       float *__restrict__ out, float inv_m,
+                                                       float *__restrict__ partial) {
+    __shared__ float box[kLX * kLY * kLZ];
+    __shared__ int red[2][4][8];
     const int64_t per_xcd = (nb + kXcd - 1) / kXcd;
     const int64_t b = (int64_t)(blockIdx.x % kXcd) * per_xcd + blockIdx.x / kXcd;
-    if (b >= nb) return;
+    if (b >= nb) return;  // whole work-group
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int per_view = tiles_u * tiles_v;
     const int j = (int)(b / per_view);
     const int rem = (int)(b - (int64_t)j * per_view);
     const int tv = rem / tiles_u, tu = rem - tv * tiles_u;
-    const int iu = tu * kTileU + (threadIdx.x & (kTileU - 1));
-    const int iv = tv * kTileV + (threadIdx.x / kTileU);
+    const int iu = tu * kBun + (t & (kBun - 1));
+    const int iv = tv * kBun + (t / kBun);
     const bool live = iu < G.nu && iv < G.nv;
-    // fastest axis of the copy to read: the one the detector's u axis follows
-    const float *eu = G.views + 12 * (int64_t)j + 6;
-    const bool swap = fabsf(eu[1] * g.inv_h[1]) > fabsf(eu[0] * g.inv_h[0]);
-    float val = 0.0f;
     Ray r;
     int k0 = 0, k1 = -1;
     bool ok = false;
@@ -317,10 +322,45 @@ __global__ __launch_bounds__(256) void project_rays(const float *__restrict__ vp
         ray_geom(G, g, j, iu, iv, r);
         ok = support_range(r, g, &k0, &k1);
     }
-    const int kw0 = __builtin_amdgcn_readfirstlane(wave_min(ok ? k0 : 0x7fffffff));
-    const int kw1 = __builtin_amdgcn_readfirstlane(wave_max(ok ? k1 : -0x7fffffff));
-    if (ok) val = swap ? march<1>(vpT, p, r, k0, k1, kw0, kw1) : march<0>(vp, p, r, k0, k1, kw0, kw1);
-    val *= G.scale;
+    int kr[6] = {ok ? k0 : 0x7fffffff, 0, 0, ok ? k1 : -0x7fffffff, 0, 0};
+    block_bounds(kr, red[1], wave, lane);
+    const int kmin = kr[0], kmax = kr[3];
+    const int sy = (int)p.px, sz = (int)p.plane;
+    float acc = 0.0f;
+    int it = 0;
+    for (int K = kmin; K <= kmax; K += kFwdChunk, ++it) {
+        const int Ke = min(K + kFwdChunk - 1, kmax);
+        const int a = max(K, k0), e = min(Ke, k1);
+        const bool has = ok && a <= e;
+        int bb[6] = {0x7fffffff, 0x7fffffff, 0x7fffffff, -0x7fffffff, -0x7fffffff, -0x7fffffff};
+        if (has) {
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) {
+                const int fa = (int)((r.U[ax] + (long long)a * r.DU[ax]) >> 32);
+                const int fe = (int)((r.U[ax] + (long long)e * r.DU[ax]) >> 32);
+                bb[ax] = min(fa, fe);
+                bb[3 + ax] = max(fa, fe);
+            }
+        }
+        block_bounds(bb, red[it & 1], wave, lane);  // alternate buffers: no reuse race
+        const int o[3] = {bb[0], bb[1], bb[2]};
+        const int nx = bb[3] - bb[0] + 2, ny = bb[4] - bb[1] + 2, nz = bb[5] - bb[2] + 2;
+        if (nx <= kLX && ny <= kLY && nz <= kLZ) {
+            // taps of the chunk: padded voxels o .. o + n - 1, inside the padded copy
+            const int n = nx * ny * nz;
+            for (int q = t; q < n; q += 256) {
+                const int lx = q % nx, rq = q / nx, ly = rq % ny, lz = rq / ny;
+                box[(lz * kLY + ly) * kLX + lx] = vp[((int64_t)(o[2] + lz) * p.py + (o[1] + ly)) * p.px + o[0] + lx];
+            }
+            __syncthreads();
+            if (has) march_span(box, kLX, kLX * kLY, o, r, a, e, acc);
+            __syncthreads();
+        } else if (has) {
+            const int o0[3] = {0, 0, 0};
+            march_span(vp, sy, sz, o0, r, a, e, acc);
+        }
+    }
+    const float val = acc * G.scale;
     const int64_t ri = ((int64_t)j * G.nv + iv) * G.nu + iu;
     if (MODE == 0) {
         if (live) out[ri] = val;
@@ -334,9 +374,9 @@ __global__ __launch_bounds__(256) void project_rays(const float *__restrict__ vp
     }
     __shared__ float ws[4];
     absr = wave_sum(absr);
-    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = absr;
+    if (lane == 0) ws[wave] = absr;
     __syncthreads();
-    if (threadIdx.x == 0) partial[b] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+    if (t == 0) partial[b] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
 }
 
 // Sum of the work-group partials in binary64, fixed order; loss = sum / M.
@@ -691,7 +731,6 @@ __global__ __launch_bounds__(256) void gather_bricks(const long long *__restrict
 // ---- workspace and entry points ------------------------------------------------
 struct ProjWs {
     float *vpad;
-    float *vpadT;
     float *partial;
     long long *staging;
     ushort4 *rect;
@@ -700,8 +739,8 @@ struct ProjWs {
 };
 
 int64_t ray_blocks(const dgr_geometry *G, int *tu, int *tv) {
-    *tu = (G->nu + kTileU - 1) / kTileU;
-    *tv = (G->nv + kTileV - 1) / kTileV;
+    *tu = (G->nu + kBun - 1) / kBun;
+    *tv = (G->nv + kBun - 1) / kBun;
     return (int64_t)G->n_views * (*tu) * (*tv);
 }
 
@@ -712,7 +751,6 @@ ProjWs carve_proj_ws(void *ws, const dgr_grid *grid, const dgr_geometry *geom) {
     int tu, tv;
     Carver f(ws);
     w.vpad = f.take<float>(pad_count(grid));
-    w.vpadT = f.take<float>(pad_count(grid));
     w.partial = f.take<float>(ray_blocks(geom, &tu, &tv));
     Carver b(ws);
     const Bricks bk = bricks_of(grid);
@@ -786,15 +824,14 @@ static dgr_status project_impl(const float *volume, const dgr_grid *grid, const 
     ProjWs w = carve_proj_ws(ws, grid, geom);
     PadDims p = pad_dims(grid);
     DevGrid g = dev_grid(grid);
-    pad_volume<<<dim3(grid_stride_blocks(pad_count(grid))), dim3(256), 0, st>>>(volume, g, p, w.vpad,
-                                                                                   w.vpadT);
+    pad_volume<<<dim3(grid_stride_blocks(pad_count(grid))), dim3(256), 0, st>>>(volume, g, p, w.vpad);
     DGR_LAUNCH_CHECK();
     int tu, tv;
     const int64_t nb = ray_blocks(geom, &tu, &tv);
     const double m = (double)geom->n_views * geom->nu * geom->nv;
     const int64_t launched = (nb + kXcd - 1) / kXcd * kXcd;
-    project_rays<MODE><<<dim3((unsigned)launched), dim3(256), 0, st>>>(
-        w.vpad, w.vpadT, p, g, geom_dev(geom), tu, tv, nb, target, out, (float)(1.0 / m), w.partial);
+    project_bundles<MODE><<<dim3((unsigned)launched), dim3(256), 0, st>>>(
+        w.vpad, p, g, geom_dev(geom), tu, tv, nb, target, out, (float)(1.0 / m), w.partial);
     DGR_LAUNCH_CHECK();
     if (MODE == 1) {
         finish_loss<<<1, 256, 0, st>>>(w.partial, nb, 1.0 / m, loss);
