@@ -64,7 +64,7 @@ def count_samples(prob) -> int:
 
 REPO = os.path.dirname(os.path.abspath(__file__))
 TRAFFIC_FILE = os.path.join(REPO, "profiles", "hbm_traffic_cone256.txt")
-KERNEL_SOURCE = {"backproject": "backproject_bricks", "project_l1": "project_rays"}
+KERNEL_SOURCE = {"backproject": "backproject_bricks", "project_l1": "project_bundles"}
 
 
 def source_digest(names=("project.hip", "internal.h")) -> str:
@@ -138,6 +138,45 @@ def recon_leg(max_iters: int):
                     "seconds_to_target": None if res["seconds"] is None else round(res["seconds"], 3),
                     "best_psnr_db": round(res["best_psnr"], 3), "best_iter": res["best_iter"],
                     "seconds_total": round(res["history"][-1][1], 2)})
+    return out
+
+
+def fvr_leg(reps: int = 5):
+    """The paper's own voxelization setting (sec. 4.2; box-size sweep of
+    Tab. 4, timing of Tab. 5): 256^3, 150,000 isotropic Gaussians (scales
+    log-uniform in [0.004, 0.03]), fixed cuboid box floor(u) +- b for box
+    edges 13..19: voxelize and voxelize backward, ms per call."""
+    from paper_2411_04844_amd import inputs, native
+    grid = inputs.cube_grid(256)
+    G = inputs.gaussians(150_000, 2001, 0.004, 0.03)
+    G["scale"][:, 1] = G["scale"][:, 0]
+    G["scale"][:, 2] = G["scale"][:, 0]
+    P = {k: torch.as_tensor(v).cuda().contiguous() for k, v in G.items()}
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    dV = torch.randn(grid.shape, generator=gen, device="cuda")
+    out = []
+    for bh in (6, 7, 8, 9):
+        ws, bws = native.Workspace(), native.Workspace()
+        pairs = native.dgr_voxelize_plan(P["mu"], P["scale"], P["quat"], grid, 0.0, bh, ws)
+        V = torch.empty(grid.shape, device="cuda")
+        grads = tuple(torch.empty_like(P[k]) for k in ("mu", "scale", "quat", "density"))
+        f = lambda: native.dgr_voxelize(P["mu"], P["scale"], P["quat"], P["density"], grid, 0.0, bh, out=V,
+                                        ws=ws, max_pairs=pairs)
+        b = lambda: native.dgr_voxelize_backward(P["mu"], P["scale"], P["quat"], P["density"], dV, grid,
+                                                 0.0, bh, ws=bws, outs=grads)
+        res = {"box": 2 * bh + 1, "tile_pairs": pairs}
+        for name, fn in (("voxelize_ms", f), ("voxelize_backward_ms", b)):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            res[name] = round(e0.elapsed_time(e1) / reps, 3)
+        native.dgr_check(ws)
+        out.append(res)
     return out
 
 
@@ -241,6 +280,8 @@ def main():
         log("timing the oracle on a sample of the workload")
         cpu = cpu_baseline(prob, args.cpu_views)
 
+    log("fixed-box voxelization sweep")
+    fvr = fvr_leg()
     rec = None
     if args.recon > 0:
         log("sparse-view loop to 35 dB")
@@ -258,6 +299,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    out["fvr_fixed_box_256^3_150k_isotropic"] = fvr
     if rec is not None:
         out["recon"] = rec
     print(json.dumps(out), flush=True)

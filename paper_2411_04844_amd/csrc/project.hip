@@ -35,7 +35,7 @@ namespace {
 
 constexpr int kPad = 2;
 constexpr int kXcd = 8;     // MI355X: work-groups are dealt round-robin to 8 XCDs
-constexpr int kB = 16;        // brick edge in cells (backward)
+constexpr int kB = 16;        // brick edge in cells (backward, <= 16: 4-bit local cells)
 constexpr int kBT = kB + 1;   // brick tile edge in voxels
 constexpr int kBT3 = kBT * kBT * kBT;
 
@@ -449,11 +449,13 @@ __device__ __forceinline__ float fixed_scale(const unsigned *maxbits, float scal
 //     lane runs (nearly) the same number of samples whatever the chord lengths
 //     of the rays, and add the eight weighted values of each sample, in fixed
 //     point, into the LDS tile.
-// The queue spans views; it is drained when it may not hold another chunk.
+// The queue spans views; it is drained when it may not hold another chunk
+// (with 320 ray slots that is after nearly every chunk of 256 candidates).
 constexpr int kChunk = 256;     // candidates per set-up pass (one per thread)
-constexpr int kRayCap = 1024;   // queued rays
-constexpr int kSegCap = 4096;   // queued segments
+constexpr int kRayCap = 320;    // queued rays
+constexpr int kSegCap = 2048;   // queued segments (>= kChunk * kMaxSeg)
 constexpr int kMaxSeg = 8;      // segments per ray (the host sizes L for this)
+static_assert(kSegCap >= kChunk * kMaxSeg && kRayCap >= kChunk, "a chunk must fit an empty queue");
 
 struct alignas(16) RayRec {  // 32 bytes
     unsigned ulo[3];  // low words of the brick-relative 32.32 position of sample k0
@@ -465,8 +467,8 @@ struct alignas(16) RayRec {  // 32 bytes
 };
 
 __device__ __forceinline__ bool in_brick(long long x, long long y, long long z) {
-    return (unsigned long long)x < (16ull << 32) && (unsigned long long)y < (16ull << 32) &&
-           (unsigned long long)z < (16ull << 32);
+    constexpr unsigned long long lim = (unsigned long long)kB << 32;
+    return (unsigned long long)x < lim && (unsigned long long)y < lim && (unsigned long long)z < lim;
 }
 
 __device__ __forceinline__ int wave_excl_scan(int v, int lane, int *total) {
@@ -563,7 +565,9 @@ __device__ __forceinline__ void march_segments(unsigned long long *tile, const R
 
 // seg_len: samples per segment, chosen on the host so that no ray in a brick
 // has more than kMaxSeg segments (and no more than 256 samples).
-__global__ __launch_bounds__(256) void backproject_bricks(const float *__restrict__ proj, DevGrid g,
+// Three work-groups per CU (54 KB of LDS each, <= 168 VGPRs): the extra waves
+// overlap one work-group's LDS adds with another's arithmetic.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void backproject_bricks(const float *__restrict__ proj, DevGrid g,
                                                           GeomDev G, Bricks bk,
                                                           const ushort4 *__restrict__ rect,
                                                           float eps, const unsigned *__restrict__ maxbits,

@@ -199,6 +199,52 @@ def evaluate(params, seeds=(3002, 59000, 59001), D=256, n=50_000, iters=600, che
     return res
 
 
+def conv_flops(D=TRAIN_D, B=None):
+    """Multiply-add flops (x2) of one forward pass on a D^3 volume."""
+    B = B or native.UNET_BASE
+    V = [D ** 3 // 8 ** l for l in range(4)]
+    layers = [(1, B, 0), (B, 2 * B, 1), (2 * B, 4 * B, 2), (4 * B, 8 * B, 3), (12 * B, 4 * B, 2),
+              (6 * B, 2 * B, 1), (3 * B, B, 0)]
+    f = sum(2 * 27 * ci * co * V[l] for ci, co, l in layers)
+    return f + 2 * B * 3 * V[0]
+
+
+def step_bench(steps=20, D=TRAIN_D, log=None):
+    """Time training steps (forward, loss, backward, Adam) on a random D^3
+    volume; returns ms per step and achieved bf16 TFLOP/s (forward + data
+    gradient + weight gradient ~ 3x the forward's flops, less the first
+    layer's data gradient)."""
+    p = init_params(1)
+    m, v = torch.zeros_like(p), torch.zeros_like(p)
+    g = torch.Generator(device="cuda").manual_seed(2)
+    x = torch.randn((D, D, D), generator=g, device="cuda")
+    tgt = torch.rand((D, D, D, 3), generator=g, device="cuda")
+    ws, lws = native.Workspace(), native.Workspace()
+
+    def one(t):
+        out = native.dgr_unet_forward(p, x, ws=ws)
+        L, d = native.dgr_unet_loss(out, tgt, ws=lws)
+        gr = native.dgr_unet_backward(p, x, d, ws)
+        native.dgr_adam(p, gr, m, v, 1e-4, t)
+
+    one(1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for t in range(steps):
+        one(t + 2)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    fw = conv_flops(D)
+    flops = 3 * fw - 2 * 27 * native.UNET_BASE * D ** 3
+    res = {"volume": D, "ms_per_step": round(ms, 3), "tflops_per_step": round(flops / 1e12, 3),
+           "achieved_tflops": round(flops / (ms * 1e-3) / 1e12, 1), "bf16_peak_tflops": 2500.0}
+    if log:
+        log(str(res))
+    return res
+
+
 def main(argv=None):
     import argparse
     import json
@@ -217,6 +263,8 @@ def main(argv=None):
     e.add_argument("--seeds", default="3002,59000,59001")
     e.add_argument("--iters", type=int, default=600)
     e.add_argument("--json", default=None)
+    sb = sub.add_parser("step-bench")
+    sb.add_argument("--steps", type=int, default=20)
     a = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)  # noqa: E731
     if a.cmd == "train":
@@ -225,6 +273,8 @@ def main(argv=None):
         params, hist = train(data, epochs=a.epochs, log=log)
         save(params, a.out)
         log(json.dumps({"pairs": a.pairs, "epochs": a.epochs, "loss": hist}))
+    elif a.cmd == "step-bench":
+        print(json.dumps(step_bench(a.steps)), flush=True)
     else:
         params = load(a.weights)
         res = evaluate(params, seeds=[int(s) for s in a.seeds.split(",")], iters=a.iters, log=log)
