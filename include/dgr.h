@@ -284,7 +284,8 @@ dgr_status dgr_conv3_forward(const uint16_t *x, int32_t x_stride, const int32_t 
                              int32_t relu, uint16_t *y, int32_t y_stride, void *stream);
 /* Backward of y = conv3(x; w) + b for dy (bfloat16 [nz][ny][nx][cout]):
  * dw (binary32 [27][cout][cin]), db (binary32 [cout]) and dx (bfloat16
- * [nz][ny][nx][cin]).  w is binary32 here (rounded to bfloat16 inside). */
+ * [nz][ny][nx][cin]).  w is binary32 here (rounded to bfloat16 inside);
+ * cin, cout multiples of 32 with cout <= 256. */
 size_t dgr_conv3_grad_workspace(const int32_t dims[3], int32_t cin, int32_t cout);
 dgr_status dgr_conv3_backward(const uint16_t *x, int32_t x_stride, const int32_t dims[3],
                               int32_t cin, const float *w, const uint16_t *dy, int32_t cout,

@@ -149,11 +149,14 @@ __global__ __launch_bounds__(256) void conv3_mfma(const u16 *__restrict__ x, int
 // ---- weight gradient ------------------------------------------------------------
 // Grid: x = 27 taps x (cout / 32) x (cin / 32) tiles, y = voxel chunks.  Each
 // work-group accumulates dW[t][co0 .. co0+31][ci0 .. ci0+31] over its chunk:
-// per 64-voxel step it stages dY[v][co] and X[v + t][ci] transposed in LDS
+// per 128-voxel step it stages dY[v][co] and X[v + t][ci] transposed in LDS
 // ([channel][voxel], so the K = voxel slice of a lane is contiguous); wave w
-// owns the 16x16 sub-tile (co0 + 16 (w / 2), ci0 + 16 (w % 2)).
-constexpr int kWgStep = 64;
-constexpr int kWgPitch = kWgStep + 8;  // u16 per LDS row (144 bytes, 16-byte aligned)
+// owns the 16x16 sub-tile (co0 + 16 (w / 2), ci0 + 16 (w % 2)) and issues 4
+// MFMAs per step.  Loader threads 0..127 stage dY, 128..255 stage X: each
+// takes 8 channels of 4 consecutive voxels and writes, per channel, the 4
+// voxels as one 64-bit LDS word.
+constexpr int kWgStep = 128;
+constexpr int kWgPitch = kWgStep + 8;  // u16 per LDS row (272 bytes, 16-byte aligned)
 
 __global__ __launch_bounds__(256) void conv3_wgrad(const u16 *__restrict__ x, int xs, Vol d, int cin,
                                                    const u16 *__restrict__ dy, int dys, int cout,
@@ -173,30 +176,39 @@ __global__ __launch_bounds__(256) void conv3_wgrad(const u16 *__restrict__ x, in
     const int64_t v_end = min(d.V, v_begin + chunk);
     const int msub = (wave >> 1) * 16, nsub = (wave & 1) * 16;
     f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    // loader: thread tid stages 8 channels (c8 = 8 (tid % 4)) of voxel tid / 4
-    // of dY, and the same of X[v + t]
-    const int lv = tid >> 2, c8 = (tid & 3) * 8;
+    const bool is_x = tid >= 128;
+    const int lt = tid & 127;
+    const int vg = (lt >> 2) * 4, c8 = (lt & 3) * 8;  // voxels vg..vg+3 of the step, channels c8..c8+7
+    u16 *dst = is_x ? Bt : At;
     for (int64_t v0 = v_begin; v0 < v_end; v0 += kWgStep) {
-        const int64_t v = v0 + lv;
-        u32x4 qa = u32x4{0u, 0u, 0u, 0u}, qb = u32x4{0u, 0u, 0u, 0u};
-        if (lv < kWgStep && v < v_end) {
-            qa = *reinterpret_cast<const u32x4 *>(dy + v * dys + cb * 32 + c8);
-            int px, py, pz;
-            vox_coords(d, v, &px, &py, &pz);
-            const int xx = px + dx, yy = py + dyy, zz = pz + dz;
-            if (xx >= 0 && yy >= 0 && zz >= 0 && xx < d.nx && yy < d.ny && zz < d.nz) {
-                const int64_t vn = ((int64_t)zz * d.ny + yy) * d.nx + xx;
-                qb = *reinterpret_cast<const u32x4 *>(x + vn * xs + ib * 32 + c8);
+        u32x4 q[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            q[i] = u32x4{0u, 0u, 0u, 0u};
+            const int64_t v = v0 + vg + i;
+            if (v < v_end) {
+                if (!is_x) {
+                    q[i] = *reinterpret_cast<const u32x4 *>(dy + v * dys + cb * 32 + c8);
+                } else {
+                    int px, py, pz;
+                    vox_coords(d, v, &px, &py, &pz);
+                    const int xx = px + dx, yy = py + dyy, zz = pz + dz;
+                    if (xx >= 0 && yy >= 0 && zz >= 0 && xx < d.nx && yy < d.ny && zz < d.nz) {
+                        const int64_t vn = ((int64_t)zz * d.ny + yy) * d.nx + xx;
+                        q[i] = *reinterpret_cast<const u32x4 *>(x + vn * xs + ib * 32 + c8);
+                    }
+                }
             }
         }
-        if (lv < kWgStep) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                At[(c8 + 2 * j) * kWgPitch + lv] = (u16)(qa[j] & 0xffffu);
-                At[(c8 + 2 * j + 1) * kWgPitch + lv] = (u16)(qa[j] >> 16);
-                Bt[(c8 + 2 * j) * kWgPitch + lv] = (u16)(qb[j] & 0xffffu);
-                Bt[(c8 + 2 * j + 1) * kWgPitch + lv] = (u16)(qb[j] >> 16);
-            }
+        for (int j = 0; j < 8; ++j) {
+            const int sh = (j & 1) * 16;
+            const unsigned long long w =
+                (unsigned long long)((q[0][j >> 1] >> sh) & 0xffffu) |
+                ((unsigned long long)((q[1][j >> 1] >> sh) & 0xffffu) << 16) |
+                ((unsigned long long)((q[2][j >> 1] >> sh) & 0xffffu) << 32) |
+                ((unsigned long long)((q[3][j >> 1] >> sh) & 0xffffu) << 48);
+            *reinterpret_cast<unsigned long long *>(dst + (c8 + j) * kWgPitch + vg) = w;
         }
         __syncthreads();
 #pragma unroll
@@ -226,18 +238,25 @@ __global__ __launch_bounds__(256) void sum_chunks(const float *__restrict__ part
     out[i] = s;
 }
 
-// Per-channel sums of a bf16 [V][s] slice (channels 0..C-1), C <= 256:
-// part[block][c] over the block's voxel range.
-constexpr int kSumBlocks = 512;
+// Per-channel sums of a bf16 [V][s] slice (channels 0..C-1), C <= 256 and a
+// divisor of 256: part[block][c] over the block's voxel range, with 256 / C
+// voxel lanes per channel summed in a fixed order at the end.
+constexpr int kSumBlocks = 1024;
 __global__ __launch_bounds__(256) void channel_sums(const u16 *__restrict__ a, int s, int C, int64_t V,
                                                     float *__restrict__ part) {
-    const int c = threadIdx.x;
-    if (c >= C) return;
+    __shared__ float red[256];
+    const int c = threadIdx.x % C, j = threadIdx.x / C, lanes = 256 / C;
     const int64_t per = (V + gridDim.x - 1) / gridDim.x;
     const int64_t v0 = (int64_t)blockIdx.x * per, v1 = min(V, v0 + per);
     float acc = 0.0f;
-    for (int64_t v = v0; v < v1; ++v) acc += bf2f(a[v * s + c]);
-    part[(int64_t)blockIdx.x * C + c] = acc;
+    for (int64_t v = v0 + j; v < v1; v += lanes) acc += bf2f(a[v * s + c]);
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (j == 0) {
+        float t = 0.0f;
+        for (int q = 0; q < lanes; ++q) t += red[q * C + c];
+        part[(int64_t)blockIdx.x * C + c] = t;
+    }
 }
 
 // ---- first layer (one input channel) on the VALU ------------------------------------
@@ -450,38 +469,51 @@ __global__ __launch_bounds__(256) void head_fwd(const u16 *__restrict__ a, int B
 }
 
 // dpre[v][c] = (sum_o dout[v][o] Wh[o][c]) * (a[v][c] > 0); block partials of
-// dWh[o][c] = sum_v dout[v][o] a[v][c] and dbh[o] (B <= 256).
+// dWh[o][c] = sum_v dout[v][o] a[v][c] and dbh[o].  256 threads = 256 / B voxel
+// lanes x B channels (B = 32), summed in a fixed order at the end.
 __global__ __launch_bounds__(256) void head_bwd(const u16 *__restrict__ a, int B, int64_t V,
                                                 const float *__restrict__ Wh, const float *__restrict__ dout,
                                                 u16 *__restrict__ dpre, float *__restrict__ part) {
-    const int c = threadIdx.x;
+    __shared__ float red[6][256];
+    const int c = threadIdx.x % B, j = threadIdx.x / B, lanes = 256 / B;
     const int64_t per = (V + gridDim.x - 1) / gridDim.x;
     const int64_t v0 = (int64_t)blockIdx.x * per, v1 = min(V, v0 + per);
     float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, b0 = 0.0f, b1 = 0.0f, b2 = 0.0f;
-    if (c < B) {
-        const float w0 = Wh[c], w1 = Wh[B + c], w2 = Wh[2 * B + c];
-        for (int64_t v = v0; v < v1; ++v) {
-            const float d0 = dout[3 * v], d1 = dout[3 * v + 1], d2 = dout[3 * v + 2];
-            const float h = bf2f(a[v * B + c]);
-            g0 = fmaf(d0, h, g0);
-            g1 = fmaf(d1, h, g1);
-            g2 = fmaf(d2, h, g2);
-            if (c == 0) {
-                b0 += d0;
-                b1 += d1;
-                b2 += d2;
-            }
-            const float s = fmaf(d0, w0, fmaf(d1, w1, d2 * w2));
-            dpre[v * B + c] = f2bf(h > 0.0f ? s : 0.0f);
+    const float w0 = Wh[c], w1 = Wh[B + c], w2 = Wh[2 * B + c];
+    for (int64_t v = v0 + j; v < v1; v += lanes) {
+        const float d0 = dout[3 * v], d1 = dout[3 * v + 1], d2 = dout[3 * v + 2];
+        const float h = bf2f(a[v * B + c]);
+        g0 = fmaf(d0, h, g0);
+        g1 = fmaf(d1, h, g1);
+        g2 = fmaf(d2, h, g2);
+        b0 += d0;
+        b1 += d1;
+        b2 += d2;
+        const float s = fmaf(d0, w0, fmaf(d1, w1, d2 * w2));
+        dpre[v * B + c] = f2bf(h > 0.0f ? s : 0.0f);
+    }
+    red[0][threadIdx.x] = g0;
+    red[1][threadIdx.x] = g1;
+    red[2][threadIdx.x] = g2;
+    red[3][threadIdx.x] = b0;
+    red[4][threadIdx.x] = b1;
+    red[5][threadIdx.x] = b2;
+    __syncthreads();
+    if (j == 0) {
+        float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
+        for (int q = 0; q < lanes; ++q) {
+            s0 += red[0][q * B + c];
+            s1 += red[1][q * B + c];
+            s2 += red[2][q * B + c];
         }
         float *o = part + (int64_t)blockIdx.x * (3 * B + 3);
-        o[c] = g0;
-        o[B + c] = g1;
-        o[2 * B + c] = g2;
-        if (c == 0) {
-            o[3 * B] = b0;
-            o[3 * B + 1] = b1;
-            o[3 * B + 2] = b2;
+        o[c] = s0;
+        o[B + c] = s1;
+        o[2 * B + c] = s2;
+        if (c < 3) {  // every channel lane saw the same voxels: take channel 0's bias sums
+            float t = 0.0f;
+            for (int q = 0; q < lanes; ++q) t += red[3 + c][q * B];
+            o[3 * B + c] = t;
         }
     }
 }
@@ -526,14 +558,21 @@ __global__ __launch_bounds__(256) void loss_final(const double *__restrict__ par
     if (threadIdx.x == 0) *loss = (float)(sh[0] / (double)V);
 }
 
-// out[i] = sum over blocks of part[block][i] (fixed order), n entries.
+// out[i] = sum over blocks of part[block][i], n entries: one work-group per
+// entry, a fixed-order tree over the block partials.
 __global__ __launch_bounds__(256) void sum_parts(const float *__restrict__ part, int nb, int n,
                                                  float *__restrict__ out) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
+    __shared__ float sh[256];
+    const int i = blockIdx.x;
     float s = 0.0f;
-    for (int b = 0; b < nb; ++b) s += part[(int64_t)b * n + i];
-    out[i] = s;
+    for (int b = threadIdx.x; b < nb; b += 256) s += part[(int64_t)b * n + i];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[i] = sh[0];
 }
 
 // ---- host side -----------------------------------------------------------------------------
@@ -595,8 +634,8 @@ struct UWs {
 };
 
 constexpr int kLossBlocks = 1024;
-constexpr int kHeadBlocks = 512;
-constexpr int kConv1Blocks = 512;
+constexpr int kHeadBlocks = 1024;
+constexpr int kConv1Blocks = 2048;
 
 int wgrad_chunks(int64_t V) { return (int)std::max<int64_t>(1, std::min<int64_t>(64, V / 16384)); }
 
@@ -683,7 +722,7 @@ dgr_status launch_wgrad(const u16 *x, int xs, const Vol &d, int cin, const u16 *
     DGR_LAUNCH_CHECK();
     channel_sums<<<kSumBlocks, 256, 0, st>>>(dy, cout, cout, d.V, part);
     DGR_LAUNCH_CHECK();
-    sum_parts<<<blocks_for(cout), 256, 0, st>>>(part, kSumBlocks, cout, db);
+    sum_parts<<<cout, 256, 0, st>>>(part, kSumBlocks, cout, db);
     DGR_LAUNCH_CHECK();
     return DGR_OK;
 }
@@ -779,7 +818,7 @@ extern "C" dgr_status dgr_unet_backward(const float *params, const float *input,
     // head
     head_bwd<<<kHeadBlocks, 256, 0, st>>>(w.dec1, B, d1.V, params + n.L[HEAD].w_off, dout, w.g_dec1, w.part);
     DGR_LAUNCH_CHECK();
-    sum_parts<<<blocks_for(3 * B + 3), 256, 0, st>>>(w.part, kHeadBlocks, 3 * B + 3, G(HEAD));
+    sum_parts<<<3 * B + 3, 256, 0, st>>>(w.part, kHeadBlocks, 3 * B + 3, G(HEAD));
     DGR_LAUNCH_CHECK();
     // dec1: input cat1, output grad g_dec1 (pre-activation)
     DGR_RET(launch_wgrad(w.cat1, 3 * B, d1, 3 * B, w.g_dec1, B, w.part, G(DEC1), Gb(DEC1), st));
@@ -817,11 +856,11 @@ extern "C" dgr_status dgr_unet_backward(const float *params, const float *input,
     DGR_LAUNCH_CHECK();
     conv1_wgrad<<<kConv1Blocks, 256, 0, st>>>(input, d1, w.g_enc1, B, B, w.part);
     DGR_LAUNCH_CHECK();
-    sum_parts<<<blocks_for(27 * B), 256, 0, st>>>(w.part, kConv1Blocks, 27 * B, G(ENC1));
+    sum_parts<<<27 * B, 256, 0, st>>>(w.part, kConv1Blocks, 27 * B, G(ENC1));
     DGR_LAUNCH_CHECK();
     channel_sums<<<kSumBlocks, 256, 0, st>>>(w.g_enc1, B, B, d1.V, w.part);
     DGR_LAUNCH_CHECK();
-    sum_parts<<<blocks_for(B), 256, 0, st>>>(w.part, kSumBlocks, B, Gb(ENC1));
+    sum_parts<<<B, 256, 0, st>>>(w.part, kSumBlocks, B, Gb(ENC1));
     DGR_LAUNCH_CHECK();
     return DGR_OK;
 }
@@ -870,7 +909,8 @@ extern "C" dgr_status dgr_conv3_backward(const uint16_t *x, int32_t x_stride, co
                                          float *dw, float *db, uint16_t *dx, void *ws, size_t ws_bytes,
                                          void *stream) {
     DGR_CHECK(x && w && dy && dw && db && dx && dims && ws, "null pointer argument");
-    DGR_CHECK(cin >= 32 && cin % 32 == 0 && cout >= 32 && cout % 32 == 0, "cin and cout must be multiples of 32");
+    DGR_CHECK(cin >= 32 && cin % 32 == 0 && cout >= 32 && cout % 32 == 0 && cout <= 256,
+              "cin and cout must be multiples of 32, cout <= 256");
     DGR_CHECK(x_stride >= cin && x_stride % 8 == 0, "x stride must cover cin and be a multiple of 8");
     DGR_CHECK(((uintptr_t)x | (uintptr_t)dy | (uintptr_t)dx) % 16 == 0, "pointers must be 16-byte aligned");
     DGR_CHECK(dims[0] >= 1 && dims[1] >= 1 && dims[2] >= 1, "dims must be >= 1");
