@@ -44,6 +44,10 @@ What pins each function (tests under ``tests/test_oracle_*.py``):
   response, its backward against the adjoint identities, pooling/upsampling
   against theirs, the network and loss gradients against central
   differences (see that module's header).
+* ``oracle.objective`` (numpy, binary64) -- the paper's full objective
+  0.6 L1 + 0.2 L_SSIM + 1 L_TV: SSIM map against a brute-force window sum,
+  SSIM(x, x) = 1, constant images against the closed form, TV of a ramp,
+  both gradients against central differences.
 """
 from __future__ import annotations
 
