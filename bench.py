@@ -117,23 +117,25 @@ def recon_leg(max_iters: int):
     the plain FDK-sampled initialisation (50,000 Gaussians of 1.5 voxels, the
     loop's specification; the same with 3-voxel Gaussians; 150,000, the
     paper's own initial count) and for the learned initialisation (50,000
-    Gaussians proposed by the U-Net)."""
+    Gaussians proposed by the U-Net); the plain ones also with the paper's
+    full objective (0.6 L1 + 0.2 SSIM + 1 TV)."""
     from paper_2411_04844_amd import learned, recon
     prob, gt = recon.sparse_view_problem(device="cuda")
     params = learned.load() if os.path.exists(learned.WEIGHTS) else None
     out = []
-    for kind, n, sv in (("plain", 50_000, 1.5), ("plain", 50_000, 3.0), ("plain", 150_000, 1.5),
-                        ("learned", 50_000, None)):
+    for kind, n, sv, obj in (("plain", 50_000, 1.5, "l1"), ("plain", 50_000, 3.0, "l1"),
+                             ("plain", 150_000, 1.5, "l1"), ("learned", 50_000, None, "l1"),
+                             ("plain", 50_000, 1.5, "full"), ("plain", 50_000, 3.0, "full")):
         if kind == "learned" and params is None:
             continue
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         prob.params = (recon.fdk_init(prob, n=n, scale_vox=sv) if kind == "plain"
                        else learned.learned_init(prob, params, n=n))
-        res = recon.reconstruct(prob, gt, max_iters=max_iters, t_start=t0,
-                                log=lambda m: log(f"recon {kind} n={n}:", m))
-        out.append({"init": kind, "gaussians": n, "scale_voxels": sv, "target_psnr_db": 35.0,
-                    "max_iters": max_iters,
+        res = recon.reconstruct(prob, gt, max_iters=max_iters, t_start=t0, objective=obj,
+                                log=lambda m: log(f"recon {kind} n={n} {obj}:", m))
+        out.append({"init": kind, "gaussians": n, "scale_voxels": sv, "objective": obj,
+                    "target_psnr_db": 35.0, "max_iters": max_iters,
                     "iterations_to_target": res["iterations"],
                     "seconds_to_target": None if res["seconds"] is None else round(res["seconds"], 3),
                     "best_psnr_db": round(res["best_psnr"], 3), "best_iter": res["best_iter"],
@@ -280,6 +282,23 @@ def main():
         log("timing the oracle on a sample of the workload")
         cpu = cpu_baseline(prob, args.cpu_views)
 
+    log("full-objective iteration (L1 + SSIM + TV)")
+    itf = recon.Iteration(prob, objective="full")
+    for _ in range(2):
+        itf.step()
+    torch.cuda.synchronize()
+    ev_f = {}
+    f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    f0.record()
+    for _ in range(5):
+        itf.step(events=ev_f)
+    f1.record()
+    torch.cuda.synchronize()
+    itf.check()
+    full = {"ms_per_iter": round(f0.elapsed_time(f1) / 5, 3),
+            "stage_ms": {k: round(float(np.mean([a.elapsed_time(b) for a, b in v])), 3) for k, v in ev_f.items()},
+            "weights": list(itf.weights)}
+    del itf
     log("fixed-box voxelization sweep")
     fvr = fvr_leg()
     rec = None
@@ -299,6 +318,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    out["full_objective_iteration"] = full
     out["fvr_fixed_box_256^3_150k_isotropic"] = fvr
     if rec is not None:
         out["recon"] = rec

@@ -210,6 +210,28 @@ dgr_status dgr_init_from_volume(const float *volume, const dgr_grid *grid, float
 dgr_status dgr_fit_density_scale(const float *p1, const float *target, int64_t m, float *density,
                                  int64_t n, double *kappa, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- the paper's full objective (sec. 4.3, App. D.1) ------------------------ */
+/* L = w1 L1(P_hat, P) + w2 L_SSIM(P_hat, P) + w3 L_TV(V), the paper's weights
+ * being 0.6, 0.2, 1.  L1 = mean |P_hat - P|; L_SSIM = 1 - mean over every view
+ * and pixel of the SSIM map (App. C.2 formula) of each 2-D view, with local
+ * statistics from an 11 x 11 Gaussian window (sigma 1.5, normalised, zero
+ * padding outside the detector), C1 = (0.01 R)^2, C2 = (0.03 R)^2;
+ * L_TV = mean over voxels of the absolute forward differences along x, y, z. */
+
+/* Projection terms: proj, target [n_views][nv][nu] (DEVICE); range R > 0, or
+ * <= 0 to use max(target).  Writes loss (DEVICE binary32 [3]) = {w1 L1 +
+ * w2 L_SSIM, L1, L_SSIM} and dproj = dL/dP_hat (overwritten).  SSIM moments,
+ * maps and their blur are binary64. */
+size_t dgr_projection_loss_workspace(int32_t n_views, int32_t nv, int32_t nu);
+dgr_status dgr_projection_loss(const float *proj, const float *target, int32_t n_views, int32_t nv,
+                               int32_t nu, float w_l1, float w_ssim, float range, float *loss,
+                               float *dproj, void *ws, size_t ws_bytes, void *stream);
+/* Volume term: loss (DEVICE binary32 [1]) = L_TV(volume); dvolume +=
+ * w_tv dL_TV/dV (accumulated into the caller's dL/dV; sign(0) = 0). */
+size_t dgr_tv_workspace(void);
+dgr_status dgr_tv(const float *volume, const dgr_grid *grid, float w_tv, float *loss, float *dvolume,
+                  void *ws, size_t ws_bytes, void *stream);
+
 /* ---- learned initialisation: a 3-D U-Net on the matrix cores -------------- */
 /* Not part of DGR (the paper initialises its Gaussians from an FBP/FDK volume,
  * Fig. 4 caption, or at random): a network that maps a one-channel volume to

@@ -80,6 +80,11 @@ _SIGS = {
     "dgr_conv3_grad_workspace": (ctypes.c_size_t, ["dims", "i32", "i32"]),
     "dgr_conv3_backward": ("st", ["p", "i32", "dims", "i32", "p", "p", "i32", "p", "p", "p", "p", "sz",
                                   "p"]),
+    "dgr_projection_loss_workspace": (ctypes.c_size_t, ["i32", "i32", "i32"]),
+    "dgr_projection_loss": ("st", ["p", "p", "i32", "i32", "i32", "f32", "f32", "f32", "p", "p", "p", "sz",
+                                   "p"]),
+    "dgr_tv_workspace": (ctypes.c_size_t, []),
+    "dgr_tv": ("st", ["p", "grid", "f32", "p", "p", "p", "sz", "p"]),
     "dgr_pool2_f32": ("st", ["p", "dims", "p", "p"]),
     "dgr_unet_targets_workspace": (ctypes.c_size_t, ["grid"]),
     "dgr_unet_targets": ("st", ["p", "p", "i64", "grid", "p", "f32", "p", "p", "sz", "p"]),
@@ -545,3 +550,36 @@ def dgr_init_from_unet(out, grid: GridSpec, n, uniforms, input_scale, ws=None):
                                                           float(input_scale), _ptr(mu), _ptr(sc), _ptr(q),
                                                           _ptr(rho), p, sz, _stream()))
     return mu, sc, q, rho
+
+
+# ---- the paper's full objective ------------------------------------------------------
+def dgr_projection_loss(proj, target, w_l1=0.6, w_ssim=0.2, range_=0.0, loss=None, dproj=None,
+                        ws: Workspace | None = None):
+    """-> (loss float32 [3] = (w1 L1 + w2 L_SSIM, L1, L_SSIM), dproj)."""
+    _need(proj, torch.float32, None, "proj")
+    _need(target, torch.float32, tuple(proj.shape), "target")
+    V, nv, nu = (int(v) for v in proj.shape)
+    if loss is None:
+        loss = torch.empty(3, dtype=torch.float32, device=proj.device)
+    if dproj is None:
+        dproj = torch.empty_like(proj)
+    ws = ws or Workspace(proj.device)
+    p, sz = ws.ptr_size(int(lib().dgr_projection_loss_workspace(V, nv, nu)))
+    _check("dgr_projection_loss", lib().dgr_projection_loss(_ptr(proj), _ptr(target), V, nv, nu, float(w_l1),
+                                                            float(w_ssim), float(range_), _ptr(loss),
+                                                            _ptr(dproj), p, sz, _stream()))
+    return loss, dproj
+
+
+def dgr_tv(volume, grid: GridSpec, dvolume, w_tv=1.0, loss=None, ws: Workspace | None = None):
+    """loss float32 [1] = L_TV; dvolume += w_tv dL_TV/dV (in place)."""
+    _need(volume, torch.float32, grid.shape, "volume")
+    _need(dvolume, torch.float32, grid.shape, "dvolume")
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=volume.device)
+    g = c_grid(grid)
+    ws = ws or Workspace(volume.device)
+    p, sz = ws.ptr_size(int(lib().dgr_tv_workspace()))
+    _check("dgr_tv", lib().dgr_tv(_ptr(volume), ctypes.byref(g), float(w_tv), _ptr(loss), _ptr(dvolume), p, sz,
+                                  _stream()))
+    return loss

@@ -39,11 +39,20 @@ class Problem:
 
 
 class Iteration:
-    """Buffers and workspaces for repeated fwd+bwd+Adam steps."""
+    """Buffers and workspaces for repeated fwd+bwd+Adam steps.
+
+    objective "l1": mean |P_hat - P| (the fused projector + L1 kernel);
+    "full": the paper's w1 L1 + w2 L_SSIM + w3 L_TV (sec. 4.3), with the
+    projection terms on P_hat and TV on the kept volume."""
 
     ORDER = ("mu", "scale", "quat", "density")
 
-    def __init__(self, prob: Problem, pair_headroom: float = 1.5):
+    def __init__(self, prob: Problem, pair_headroom: float = 1.5, objective: str = "l1",
+                 weights=(0.6, 0.2, 1.0)):
+        if objective not in ("l1", "full"):
+            raise ValueError(f"unknown objective {objective!r}")
+        self.objective = objective
+        self.weights = tuple(float(w) for w in weights)
         self.p = prob
         dev = prob.target.device
         self.vox_ws = native.Workspace(dev)
@@ -68,6 +77,16 @@ class Iteration:
         # allocate the workspaces once, outside any timed region
         self.vox_ws.get(native.dgr_voxelize_workspace(P["mu"].shape[0], self.max_pairs, prob.grid))
         self.proj_ws.get(native.dgr_project_workspace(prob.grid, prob.geom, prob.views))
+        if objective == "full":
+            self.P = torch.empty_like(prob.target)
+            self.loss = torch.zeros(3, dtype=torch.float32, device=dev)
+            self.tv_value = torch.zeros(1, dtype=torch.float32, device=dev)
+            self.obj_ws, self.tv_ws = native.Workspace(dev), native.Workspace(dev)
+            g = prob.geom
+            self.obj_ws.get(int(native.lib().dgr_projection_loss_workspace(g.n_views, g.nv, g.nu)))
+            self.tv_ws.get(int(native.lib().dgr_tv_workspace()))
+            self.STAGES = ("voxelize", "project", "projection_loss", "backproject", "tv",
+                           "voxelize_backward", "adam")
 
     # individual stages (each one C-ABI call or a few)
     def voxelize(self):
@@ -79,6 +98,23 @@ class Iteration:
         pr = self.p
         native.dgr_project_l1(self.V, pr.target, pr.grid, pr.geom, pr.views, loss=self.loss,
                               dproj=self.dproj, ws=self.proj_ws)
+
+    def project(self):
+        pr = self.p
+        native.dgr_project(self.V, pr.grid, pr.geom, pr.views, out=self.P, ws=self.proj_ws)
+
+    def projection_loss(self):
+        native.dgr_projection_loss(self.P, self.p.target, self.weights[0], self.weights[1], loss=self.loss,
+                                   dproj=self.dproj, ws=self.obj_ws)
+
+    def tv(self):
+        native.dgr_tv(self.V, self.p.grid, self.dV, self.weights[2], loss=self.tv_value, ws=self.tv_ws)
+
+    def total_loss(self) -> float:
+        """The objective's value (synchronises)."""
+        if self.objective == "l1":
+            return float(self.loss)
+        return float(self.loss[0]) + self.weights[2] * float(self.tv_value[0])
 
     def backproject(self):
         pr = self.p
@@ -194,7 +230,7 @@ def random_init(prob: Problem, n=50_000, seed=3005, s_lo=0.004, s_hi=0.03):
 
 
 def reconstruct(prob: Problem, gt, max_iters=5000, target_psnr=35.0, check_every=10, log=None,
-                t_start=None, lr_final_frac=1.0, decay_iters=None):
+                t_start=None, lr_final_frac=1.0, decay_iters=None, objective="l1"):
     """Run fwd+bwd+Adam iterations until the volume PSNR against gt reaches
     target_psnr (checked every check_every iterations) or max_iters.
 
@@ -204,7 +240,7 @@ def reconstruct(prob: Problem, gt, max_iters=5000, target_psnr=35.0, check_every
     the iteration count, seconds since t_start and the history."""
     import time
     t0 = time.perf_counter() if t_start is None else t_start
-    it = Iteration(prob)
+    it = Iteration(prob, objective=objective)
     decay_iters = decay_iters or max_iters
     psnr_out = torch.empty(3, dtype=torch.float64, device=prob.target.device)
     hist = []
@@ -218,9 +254,10 @@ def reconstruct(prob: Problem, gt, max_iters=5000, target_psnr=35.0, check_every
             val = float(psnr_out[0])  # synchronises
             it.check()
             it.replan()
-            hist.append((i, time.perf_counter() - t0, val, float(it.loss)))
+            loss = it.total_loss()
+            hist.append((i, time.perf_counter() - t0, val, loss))
             if log:
-                log(f"iter {i}: PSNR {val:.2f} dB, loss {float(it.loss):.5g}, "
+                log(f"iter {i}: PSNR {val:.2f} dB, loss {loss:.5g}, "
                     f"{time.perf_counter() - t0:.1f}s")
             if val >= target_psnr:
                 reached = i
