@@ -210,6 +210,47 @@ dgr_status dgr_init_from_volume(const float *volume, const dgr_grid *grid, float
 dgr_status dgr_fit_density_scale(const float *p1, const float *target, int64_t m, float *density,
                                  int64_t n, double *kappa, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- adaptive density control (Alg. 2) ------------------------------------- */
+/* A Gaussian set with its Adam moments (DEVICE, binary32): mu/scale [n][3],
+ * quat [n][4], density [n]; m_* and v_* the first and second moments. */
+typedef struct dgr_gaussians {
+    float *mu, *scale, *quat, *density;
+    float *m_mu, *m_scale, *m_quat, *m_density;
+    float *v_mu, *v_scale, *v_quat, *v_density;
+} dgr_gaussians;
+
+/* Thresholds: iters = iterations accumulated in acc; tau = minimum averaged
+ * position gradient to clone or split; tau_prune = near-zero gradient that
+ * prunes; theta = scale separating clone (<=) from split (>) (the paper:
+ * 0.005 of the body diagonal); size_vox = box edge in voxels (prune when the
+ * largest scale exceeds 3 x size voxels); n_max = cap on the set's size. */
+typedef struct dgr_densify_params {
+    int32_t iters;
+    float tau, tau_prune, theta, size_vox;
+    int64_t n_max;
+} dgr_densify_params;
+
+/* acc[g] += ||dmu[g]||_2 (dmu [n][3]), after each iteration's backward. */
+dgr_status dgr_accumulate_grad_norm(const float *dmu, int64_t n, float *acc, void *stream);
+
+/* One pass of Alg. 2 from src (n Gaussians) into dst (capacity >= n_max; the
+ * arrays of src and dst must not overlap).  avg = acc / iters (binary32);
+ * sigma = largest scale.  Clone: avg >= tau, sigma <= theta; split: avg >=
+ * tau, sigma > theta; each limited to the room left under n_max, largest avg
+ * first (ties: lower index), clones before splits.  A clone and its original
+ * carry half the density (the copy's moments start at zero); a split
+ * Gaussian is replaced by two with means mu + R diag(s) z_k (normals
+ * [n][2][3], standard normal draws supplied by the caller), scales s/2^(1/3),
+ * zero moments.  Other Gaussians are pruned if avg <= tau_prune, density <= 0
+ * or sigma > 3 size_vox / min(inv_h).  dst holds the survivors in index order
+ * (0, 1 or 2 entries per source Gaussian).  Synchronising: *n_out (HOST) is
+ * the new count, counts (HOST) = {cloned, split, pruned}. */
+size_t dgr_densify_workspace(int64_t n);
+dgr_status dgr_densify(const dgr_gaussians *src, int64_t n, const float *acc, const float *normals,
+                       const dgr_grid *grid, const dgr_densify_params *params,
+                       const dgr_gaussians *dst, int64_t *n_out, int64_t counts[3], void *ws,
+                       size_t ws_bytes, void *stream);
+
 /* ---- the paper's full objective (sec. 4.3, App. D.1) ------------------------ */
 /* L = w1 L1(P_hat, P) + w2 L_SSIM(P_hat, P) + w3 L_TV(V), the paper's weights
  * being 0.6, 0.2, 1.  L1 = mean |P_hat - P|; L_SSIM = 1 - mean over every view

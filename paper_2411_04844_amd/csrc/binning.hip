@@ -243,6 +243,11 @@ dgr_status exclusive_scan_f64(const float *in, double *out, int64_t n, double *b
     return exclusive_scan<float, double, double>(in, out, n, blk, total, st);
 }
 
+dgr_status exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *blk, uint32_t *total,
+                              hipStream_t st) {
+    return exclusive_scan<uint32_t, uint32_t, uint32_t>(in, out, n, blk, total, st);
+}
+
 VoxWs carve_vox_ws(void *ws, int64_t n, int64_t cap, const dgr_grid *grid) {
     VoxWs w{};
     Carver c(ws);

@@ -190,6 +190,9 @@ dgr_status enqueue_count_only(const float *mu, const float *scale, const float *
 int64_t scan_f64_blocks(int64_t n);
 dgr_status exclusive_scan_f64(const float *in, double *out, int64_t n, double *blk, double *total,
                               hipStream_t st);
+// uint32 exclusive scan (sums below 2^32); blk needs scan_f64_blocks(n) entries.
+dgr_status exclusive_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *blk, uint32_t *total,
+                              hipStream_t st);
 
 inline int64_t tiles_of(const dgr_grid *g) {
     return (int64_t)((g->dims[0] + 7) / 8) * ((g->dims[1] + 7) / 8) * ((g->dims[2] + 7) / 8);

@@ -41,6 +41,16 @@ class DgrGeometry(ctypes.Structure):
                 ("length_scale", ctypes.c_float)]
 
 
+class DgrGaussians(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("mu", "scale", "quat", "density", "m_mu", "m_scale", "m_quat",
+                                               "m_density", "v_mu", "v_scale", "v_quat", "v_density")]
+
+
+class DgrDensifyParams(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("tau", ctypes.c_float), ("tau_prune", ctypes.c_float),
+                ("theta", ctypes.c_float), ("size_vox", ctypes.c_float), ("n_max", ctypes.c_int64)]
+
+
 _lib = None
 _SIGS = {
     "dgr_voxelize_workspace": (ctypes.c_size_t, ["i64", "i64", "grid"]),
@@ -80,6 +90,9 @@ _SIGS = {
     "dgr_conv3_grad_workspace": (ctypes.c_size_t, ["dims", "i32", "i32"]),
     "dgr_conv3_backward": ("st", ["p", "i32", "dims", "i32", "p", "p", "i32", "p", "p", "p", "p", "sz",
                                   "p"]),
+    "dgr_accumulate_grad_norm": ("st", ["p", "i64", "p", "p"]),
+    "dgr_densify_workspace": (ctypes.c_size_t, ["i64"]),
+    "dgr_densify": ("st", ["gs", "i64", "p", "p", "grid", "dens", "gs", "p", "p", "p", "sz", "p"]),
     "dgr_projection_loss_workspace": (ctypes.c_size_t, ["i32", "i32", "i32"]),
     "dgr_projection_loss": ("st", ["p", "p", "i32", "i32", "i32", "f32", "f32", "f32", "p", "p", "p", "sz",
                                    "p"]),
@@ -97,7 +110,8 @@ _SIGS = {
 _CT = {"p": ctypes.c_void_p, "i64": ctypes.c_int64, "i32": ctypes.c_int32, "f32": ctypes.c_float,
        "sz": ctypes.c_size_t, "grid": ctypes.POINTER(DgrGrid), "trunc": ctypes.POINTER(DgrTrunc),
        "geom": ctypes.POINTER(DgrGeometry), "st": ctypes.c_int,
-       "dims": ctypes.POINTER(ctypes.c_int32)}
+       "dims": ctypes.POINTER(ctypes.c_int32), "gs": ctypes.POINTER(DgrGaussians),
+       "dens": ctypes.POINTER(DgrDensifyParams)}
 
 
 def lib():
@@ -583,3 +597,53 @@ def dgr_tv(volume, grid: GridSpec, dvolume, w_tv=1.0, loss=None, ws: Workspace |
     _check("dgr_tv", lib().dgr_tv(_ptr(volume), ctypes.byref(g), float(w_tv), _ptr(loss), _ptr(dvolume), p, sz,
                                   _stream()))
     return loss
+
+
+# ---- adaptive density control ----------------------------------------------------------
+GROUPS = ("mu", "scale", "quat", "density")
+WIDTH = {"mu": 3, "scale": 3, "quat": 4, "density": 1}
+
+
+def dgr_accumulate_grad_norm(dmu, acc):
+    _need(dmu, torch.float32, None, "dmu")
+    _need(acc, torch.float32, (dmu.shape[0],), "acc")
+    _check("dgr_accumulate_grad_norm", lib().dgr_accumulate_grad_norm(_ptr(dmu), dmu.shape[0], _ptr(acc),
+                                                                      _stream()))
+
+
+def _gauss_struct(P, m, v):
+    g = DgrGaussians()
+    for k in GROUPS:
+        setattr(g, k, P[k].data_ptr())
+        setattr(g, "m_" + k, m[k].data_ptr())
+        setattr(g, "v_" + k, v[k].data_ptr())
+    return g
+
+
+def dgr_densify(P, m, v, acc, normals, grid: GridSpec, dst, iters, tau, tau_prune, theta, size_vox, n_max,
+                ws: Workspace | None = None):
+    """One pass of Alg. 2.  P, m, v: dicts of the current Gaussians and Adam
+    moments (n rows); dst: (P', m', v') dicts with at least n_max rows.
+    Returns (new n, (cloned, split, pruned)) (synchronising)."""
+    n = P["mu"].shape[0]
+    for k in GROUPS:
+        shp = (n,) if k == "density" else (n, WIDTH[k])
+        for name, t in (("P", P[k]), ("m", m[k]), ("v", v[k])):
+            _need(t, torch.float32, shp, f"{name}[{k}]")
+        for t in dst:
+            if not (t[k].is_cuda and t[k].is_contiguous() and t[k].shape[0] >= n_max):
+                raise ValueError(f"destination {k} must hold n_max rows")
+    _need(acc, torch.float32, (n,), "acc")
+    _need(normals, torch.float32, (n, 2, 3), "normals")
+    src = _gauss_struct(P, m, v)
+    d = _gauss_struct(*dst)
+    prm = DgrDensifyParams(int(iters), float(tau), float(tau_prune), float(theta), float(size_vox), int(n_max))
+    g = c_grid(grid)
+    n_out = ctypes.c_int64(0)
+    counts = (ctypes.c_int64 * 3)()
+    ws = ws or Workspace(acc.device)
+    p, sz = ws.ptr_size(int(lib().dgr_densify_workspace(n)))
+    _check("dgr_densify", lib().dgr_densify(ctypes.byref(src), n, _ptr(acc), _ptr(normals), ctypes.byref(g),
+                                            ctypes.byref(prm), ctypes.byref(d), ctypes.byref(n_out), counts, p,
+                                            sz, _stream()))
+    return int(n_out.value), (int(counts[0]), int(counts[1]), int(counts[2]))

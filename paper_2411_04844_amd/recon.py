@@ -134,6 +134,17 @@ class Iteration:
 
     STAGES = ("voxelize", "project_l1", "backproject", "voxelize_backward", "adam")
 
+    def set_gaussians(self, P, m, v, headroom: float = 1.5):
+        """Install a new Gaussian set with its Adam moments (after density
+        control): fresh gradient buffers and a re-planned pair capacity."""
+        pr = self.p
+        pr.params, self.m, self.v = P, m, v
+        self.grads = {k: torch.empty_like(P[k]) for k in self.ORDER}
+        pairs = native.dgr_voxelize_plan(P["mu"], P["scale"], P["quat"], pr.grid, pr.k_sigma, pr.box_half,
+                                         self.vox_ws)
+        self.max_pairs = int(pairs * headroom) + 1024
+        self.vox_ws.get(native.dgr_voxelize_workspace(P["mu"].shape[0], self.max_pairs, pr.grid))
+
     def step(self, events=None):
         """One iteration; with `events` (dict stage -> list), HIP events
         bracket each stage on the current stream."""
@@ -162,6 +173,53 @@ class Iteration:
             self.vox_ws.get(native.dgr_voxelize_workspace(P["mu"].shape[0], self.max_pairs,
                                                           pr.grid))
         return pairs
+
+
+class DensityControl:
+    """Alg. 2 on the GPU: ||dL/dmu|| accumulated every iteration, a clone /
+    split / prune pass (dgr_densify) every `every` iterations, n capped at
+    n_max.  theta defaults to 0.005 of the grid's body diagonal.  Split draws
+    are standard normals from a seeded generator."""
+
+    def __init__(self, prob: Problem, n_max=500_000, every=100, tau=2e-5, tau_prune=1e-9, theta=None,
+                 size_vox=17.0, seed=3006):
+        g = prob.grid
+        diag = sum((g.dims[a] / g.inv_h[a]) ** 2 for a in range(3)) ** 0.5
+        self.theta = 0.005 * diag if theta is None else theta
+        self.n_max, self.every, self.tau, self.tau_prune, self.size_vox = n_max, every, tau, tau_prune, size_vox
+        dev = prob.target.device
+        self.bufs = []
+        for _ in range(2):
+            trio = []
+            for _ in range(3):
+                trio.append({k: torch.empty((n_max,) + (() if k == "density" else (native.WIDTH[k],)),
+                                            dtype=torch.float32, device=dev) for k in Iteration.ORDER})
+            self.bufs.append(tuple(trio))
+        self.cur = None  # which buffer holds the current set (None: the problem's own tensors)
+        self.acc = torch.zeros(prob.params["mu"].shape[0], dtype=torch.float32, device=dev)
+        self.gen = torch.Generator(device=dev).manual_seed(seed)
+        self.ws = native.Workspace(dev)
+        self.log = []
+
+    def accumulate(self, it: "Iteration"):
+        native.dgr_accumulate_grad_norm(it.grads["mu"], self.acc)
+
+    def densify(self, it: "Iteration", iteration: int):
+        P = it.p.params
+        n = P["mu"].shape[0]
+        dst_i = 0 if self.cur != 0 else 1
+        dst = self.bufs[dst_i]
+        normals = torch.randn((n, 2, 3), generator=self.gen, device=self.acc.device)
+        n_new, counts = native.dgr_densify(P, it.m, it.v, self.acc, normals, it.p.grid, dst, self.every,
+                                           self.tau, self.tau_prune, self.theta, self.size_vox, self.n_max,
+                                           ws=self.ws)
+        it.set_gaussians({k: dst[0][k][:n_new] for k in Iteration.ORDER},
+                         {k: dst[1][k][:n_new] for k in Iteration.ORDER},
+                         {k: dst[2][k][:n_new] for k in Iteration.ORDER})
+        self.cur = dst_i
+        self.acc = torch.zeros(n_new, dtype=torch.float32, device=self.acc.device)
+        self.log.append((iteration, n, n_new) + counts)
+        return n_new, counts
 
 
 # --------------------------------------------------------------------------
@@ -230,17 +288,21 @@ def random_init(prob: Problem, n=50_000, seed=3005, s_lo=0.004, s_hi=0.03):
 
 
 def reconstruct(prob: Problem, gt, max_iters=5000, target_psnr=35.0, check_every=10, log=None,
-                t_start=None, lr_final_frac=1.0, decay_iters=None, objective="l1"):
+                t_start=None, lr_final_frac=1.0, decay_iters=None, objective="l1", density_control=None):
     """Run fwd+bwd+Adam iterations until the volume PSNR against gt reaches
     target_psnr (checked every check_every iterations) or max_iters.
 
     lr_final_frac < 1 decays every rate exponentially to that fraction over
     decay_iters iterations (default max_iters) and holds it there; the paper
     decays its rate tenfold over training (sec. 5.1).  Returns a dict with
-    the iteration count, seconds since t_start and the history."""
+    the iteration count, seconds since t_start and the history.
+
+    density_control: None, or a dict of DensityControl arguments (Alg. 2
+    every `every` iterations)."""
     import time
     t0 = time.perf_counter() if t_start is None else t_start
     it = Iteration(prob, objective=objective)
+    dc = DensityControl(prob, **density_control) if density_control is not None else None
     decay_iters = decay_iters or max_iters
     psnr_out = torch.empty(3, dtype=torch.float64, device=prob.target.device)
     hist = []
@@ -248,6 +310,13 @@ def reconstruct(prob: Problem, gt, max_iters=5000, target_psnr=35.0, check_every
     for i in range(1, max_iters + 1):
         it.lr_factor = lr_final_frac ** (min(i - 1, decay_iters) / decay_iters)
         it.step()
+        if dc is not None:
+            dc.accumulate(it)
+            if i % dc.every == 0 and i < max_iters:
+                n_new, counts = dc.densify(it, i)
+                if log:
+                    log(f"iter {i}: density control -> {n_new} Gaussians (cloned {counts[0]}, split "
+                        f"{counts[1]}, pruned {counts[2]})")
         if i % check_every == 0 or i == max_iters:
             it.voxelize()
             native.dgr_psnr(it.V, gt, out=psnr_out)
@@ -263,7 +332,8 @@ def reconstruct(prob: Problem, gt, max_iters=5000, target_psnr=35.0, check_every
                 reached = i
                 break
     best = max(hist, key=lambda h: h[2]) if hist else None
-    return {"iterations": reached, "seconds": (time.perf_counter() - t0) if reached else None,
+    extra = {"density_control": dc.log} if dc is not None else {}
+    return {**extra, "iterations": reached, "seconds": (time.perf_counter() - t0) if reached else None,
             "final_psnr": hist[-1][2] if hist else None,
             "best_psnr": best[2] if best else None, "best_iter": best[0] if best else None,
             "history": hist}
