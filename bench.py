@@ -28,7 +28,8 @@ METRIC = "fwd+bwd ms/iter @256^3,100k Gaussians,360 views; s to 35 dB PSNR vs pl
 HBM_PEAK_GBS = 8000.0
 FP32_VALU_PEAK_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz, no packed FP32
 
-# Algorithmic work per unit (measurement section)
+# Algorithmic work per ray sample: position, weights, seven lerps and the sum
+# (forward); position, weights, eight products (backward)
 FLOP_PER_SAMPLE = {"project_l1": 31.0, "backproject": 34.0}
 
 
@@ -230,8 +231,8 @@ def main():
                     help="only run a 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path "
+              "(the path would shard by views, one all-reduce of the parameter gradient)", file=sys.stderr)
         sys.exit(2)
 
     if args.copy_calibration:

@@ -45,7 +45,7 @@ GRIDS = {
 }
 
 
-def config1_gaussians(n=2000, seed=1001):
+def small_gaussians(n=2000, seed=1001):
     return inputs.gaussians(n, seed, 0.01, 0.05)
 
 
@@ -101,15 +101,15 @@ def _vox_pair(G, grid, k_sigma=3.0, bh=8):
     return got, want
 
 
-def test_voxelize_config1_brute_force():
+def test_voxelize_64cube_2000_brute_force():
     grid = inputs.cube_grid(64)
-    say("voxelize config1")
-    G = config1_gaussians()
+    say("voxelize 64^3 / 2000")
+    G = small_gaussians()
     got = native.dgr_voxelize(*gauss_dev(G), grid).cpu().numpy()
     box = oracle.bbox(G["mu"], G["scale"], G["quat"], grid.dims, grid.lo, grid.inv_h)
     want = oracle.voxelize(G["mu"], G["scale"], G["quat"], G["density"], grid.dims, grid.lo,
                            grid.inv_h, box, brute=True)
-    say("voxelize config1 rel_l2", rel_l2(got, want))
+    say("voxelize 64^3 / 2000 rel_l2", rel_l2(got, want))
     assert rel_l2(got, want) < TOL
 
 
@@ -149,7 +149,7 @@ def test_voxelize_empty_and_single():
 def test_voxelize_deterministic_and_capacity_error():
     grid = inputs.cube_grid(64)
     say("voxelize determinism")
-    G = config1_gaussians()
+    G = small_gaussians()
     a = native.dgr_voxelize(*gauss_dev(G), grid)
     b = native.dgr_voxelize(*gauss_dev(G), grid)
     assert torch.equal(a, b)
@@ -166,7 +166,7 @@ def test_voxelize_deterministic_and_capacity_error():
 # --------------------------------------------------------------------------
 # projection, L1, backprojection
 # --------------------------------------------------------------------------
-def config1_geometry():
+def small_parallel_geometry():
     h = 2.0 / 64
     return inputs.parallel_geometry(50, 64, 64, h, h / 2)
 
@@ -182,7 +182,7 @@ def _geoms():
     grid_p = inputs.cube_grid(64)
     grid_c = inputs.GridSpec((48, 44, 40), (-1.0, -1.0 * 44 / 48, -1.0 * 40 / 48), (24.0, 24.0, 24.0))
     cone = inputs.cone_geometry(10, 70, 45, 0.02, 7.8125, 11.71875, 1.0 / 48, arc=2 * math.pi)
-    return {"parallel": (grid_p, config1_geometry()), "cone": (grid_c, cone)}
+    return {"parallel": (grid_p, small_parallel_geometry()), "cone": (grid_c, cone)}
 
 
 @pytest.mark.parametrize("kind", ["parallel", "cone"])
