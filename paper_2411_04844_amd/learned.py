@@ -252,9 +252,9 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description="learned initialisation: train or evaluate the U-Net")
     sub = ap.add_subparsers(dest="cmd", required=True)
     t = sub.add_parser("train")
-    t.add_argument("--pairs", type=int, default=160)
+    t.add_argument("--pairs", type=int, default=600)
     t.add_argument("--first-seed", type=int, default=50_000)
-    t.add_argument("--epochs", type=int, default=12)
+    t.add_argument("--epochs", type=int, default=8)
     t.add_argument("--gaussians", type=int, default=20_000)
     t.add_argument("--iters", type=int, default=150)
     t.add_argument("--out", default=WEIGHTS)
