@@ -81,6 +81,7 @@ typedef struct {
 
 #define DGR_PARALLEL 0
 #define DGR_CONE 1
+#define DGR_FAN 2
 
 /* Acquisition geometry.  The paper leaves the projection T abstract
  * (sec. 4.3); the operator here is the trilinear ray march
@@ -90,9 +91,17 @@ typedef struct {
  * zero outside the grid.
  * views: DEVICE pointer, binary32 [n_views][12] =
  *   { a[3], det[3], e_u[3], e_v[3] }  (world units)
- * a is the ray direction (DGR_PARALLEL) or the source position (DGR_CONE);
+ * a is the ray direction (DGR_PARALLEL), the source position (DGR_CONE) or
+ * the source position of the central row (DGR_FAN: row iv has its own
+ * source a + (iv-(nv-1)/2)*e_v, so each detector row is a 2-D fan beam in
+ * its own plane -- a stack of fan-beam slices, the geometry of the paper's
+ * fan-beam sparse-view and limited-angle experiments, sec. 5.1, Tabs. 2-3);
  * detector pixel (iu, iv) is centred at det + (iu-(nu-1)/2)*e_u +
- * (iv-(nv-1)/2)*e_v.  Projections are stored [n_views][nv][nu].            */
+ * (iv-(nv-1)/2)*e_v.  Projections are stored [n_views][nv][nu].
+ * DGR_FAN is meant for e_v orthogonal to e_u and to det - a (each row's fan
+ * then lies in a plane orthogonal to e_v); the operator is defined for any
+ * vectors, and views that break this are handled exactly but without the
+ * detector-footprint culling, so they run slower.                         */
 typedef struct {
     int32_t kind;
     int32_t n_views, nu, nv;
@@ -177,9 +186,14 @@ dgr_status dgr_adam(float *param, const float *grad, float *m, float *v, int64_t
  * n_views equal steps (arc = 2*pi): cosine weighting, Ram-Lak ramp filter
  * along detector rows (spacing |e_u| R/D at the isocentre), and voxel-driven
  * backprojection with weight (dbeta/2)(R/U)^2, divided by length_scale.
- * proj [n_views][nv][nu] -> volume [nz][ny][nx] (overwritten).  geom must be
- * DGR_CONE with nu <= 8192 (a filtered row is staged in LDS in binary64).
- * Returns DGR_ERR_INVALID_ARG otherwise; all pointers are DEVICE pointers. */
+ * With a DGR_FAN geometry the same steps use each row's own source, which
+ * makes it slice-by-slice fan-beam FBP: the cosine weight sees only the
+ * in-row offset, and a voxel is read from the row whose fan plane holds it,
+ * row position ((x - a).m)/(e_v.m) with m = (det - a) x e_u, linear between
+ * rows.  proj [n_views][nv][nu] -> volume [nz][ny][nx] (overwritten).  geom
+ * must be DGR_CONE or DGR_FAN with nu <= 8192 (a filtered row is staged in
+ * LDS in binary64).  Returns DGR_ERR_INVALID_ARG otherwise; all pointers are
+ * DEVICE pointers. */
 size_t dgr_fdk_workspace(const dgr_grid *grid, const dgr_geometry *geom);
 dgr_status dgr_fdk(const float *proj, const dgr_grid *grid, const dgr_geometry *geom, float arc,
                    float *volume, void *ws, size_t ws_bytes, void *stream);

@@ -106,7 +106,7 @@ def lib():
         L.orc_adam.restype = None
         L.orc_psnr.argtypes = [P, P, i64]
         L.orc_psnr.restype = f64
-        L.orc_fdk.argtypes = [P, i32, i32, i32, P, f64, f64, P, P, P, P]
+        L.orc_fdk.argtypes = [P, i32, i32, i32, i32, P, f64, f64, P, P, P, P]
         L.orc_fdk.restype = None
         L.orc_init_from_volume.argtypes = [P, P, P, P, f64, i64, P, f64, P, P, P, P, P]
         L.orc_init_from_volume.restype = i64
@@ -239,13 +239,14 @@ def adam(p, g, m, v, lr, t, b1=0.9, b2=0.999, eps=1e-8):
                    float(eps), int(t))
 
 
-def fdk(proj, views, nu, nv, arc, length_scale, dims, lo, inv_h):
-    """FDK volume float64 [nz, ny, nx] from cone-beam projections."""
+def fdk(proj, views, nu, nv, arc, length_scale, dims, lo, inv_h, kind=1):
+    """FDK volume float64 [nz, ny, nx] from cone-beam projections (kind 1),
+    or slice-by-slice fan-beam FBP (kind 2)."""
     proj = _c(proj, np.float32)
     views = _c(views, np.float32)
     d, l, h = _grid_args(dims, lo, inv_h, np.float64)
     V = np.zeros((dims[2], dims[1], dims[0]), np.float64)
-    lib().orc_fdk(_p(proj), views.shape[0], int(nu), int(nv), _p(views), float(arc),
+    lib().orc_fdk(_p(proj), int(kind), views.shape[0], int(nu), int(nv), _p(views), float(arc),
                   float(length_scale), _p(d), _p(l), _p(h), _p(V))
     return V
 

@@ -369,6 +369,10 @@ void orc_voxelize_grad(const double *mu, const double *scale, const double *quat
 /* outside the grid.  views[12*j] = {a[3], det[3], e_u[3], e_v[3]}: a is    */
 /* the ray direction (parallel, kind 0) or the source point (cone, kind 1); */
 /* pixel (iu, iv) sits at det + (iu - (nu-1)/2) e_u + (iv - (nv-1)/2) e_v.  */
+/* Fan beam (kind 2), the slice stacks of the paper's fan-beam experiments  */
+/* (sec. 5.1, Tabs. 2-3): every detector row is a 2-D fan with its own      */
+/* source, a + (iv - (nv-1)/2) e_v, the central row's source shifted with   */
+/* the row.                                                                  */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     int32_t kind, n_views, nu, nv;
@@ -385,8 +389,13 @@ static void ray_of(const orc_geom *G, int64_t j, int64_t iu, int64_t iv, double 
     for (int a = 0; a < 3; ++a) pix[a] = (double)v[3 + a] + au * (double)v[6 + a] + av * (double)v[9 + a];
     if (G->kind == 0) {
         for (int a = 0; a < 3; ++a) { d[a] = v[a]; o[a] = pix[a]; }
-    } else {
+    } else if (G->kind == 1) {
         for (int a = 0; a < 3; ++a) { d[a] = pix[a] - (double)v[a]; o[a] = v[a]; }
+    } else {
+        for (int a = 0; a < 3; ++a) {
+            o[a] = (double)v[a] + av * (double)v[9 + a];
+            d[a] = pix[a] - o[a];
+        }
     }
     double nd = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     for (int a = 0; a < 3; ++a) d[a] /= nd;
@@ -661,6 +670,11 @@ int orc_num_threads(void)
 /*  3. f(x) += (dbeta / 2) (R / U)^2 q(a(x), b(x)), U = (x - s).n, (a, b)   */
 /*     the detector position of the ray s -> x, bilinear in q, zero outside.*/
 /* The result is divided by length_scale (projections carry that factor).   */
+/* Fan beam (kind 2): 2-D fan-beam FBP of each slice is the same three      */
+/* steps with the row's own source s_b = s + b e_v: in step 1 |pix - s_b|   */
+/* has no e_v part; in step 3 x is read from the row b whose fan plane      */
+/* holds it, b = ((x - s).m) / (e_v.m) with m = (det - s) x e_u, R and U    */
+/* taken from s_b.                                                          */
 /* ------------------------------------------------------------------------ */
 static void view_frame(const float *v, double s[3], double det[3], double eu[3], double ev[3],
                        double n[3], double *D, double *R)
@@ -677,10 +691,11 @@ static void view_frame(const float *v, double s[3], double det[3], double eu[3],
     *R = -(s[0] * n[0] + s[1] * n[1] + s[2] * n[2]);
 }
 
-void orc_fdk(const float *proj, int32_t n_views, int32_t nu, int32_t nv, const float *views,
+void orc_fdk(const float *proj, int32_t kind, int32_t n_views, int32_t nu, int32_t nv, const float *views,
              double arc, double length_scale, const int32_t dims[3], const double glo[3],
              const double inv_h[3], double *V)
 {
+    int fan = kind == 2;
     int64_t npix = (int64_t)nu * nv;
     double *q = malloc(sizeof(double) * (size_t)(n_views * npix));
 #pragma omp parallel for schedule(dynamic, 1)
@@ -694,7 +709,8 @@ void orc_fdk(const float *proj, int32_t n_views, int32_t nu, int32_t nv, const f
         for (int64_t iu = 0; iu < nu; ++iu) {
             double au = (double)iu - 0.5 * (nu - 1), av = (double)iv - 0.5 * (nv - 1), r2 = 0.0;
             for (int a = 0; a < 3; ++a) {
-                double d = det[a] + au * eu[a] + av * ev[a] - s[a];
+                double src = fan ? s[a] + av * ev[a] : s[a];
+                double d = det[a] + au * eu[a] + av * ev[a] - src;
                 r2 += d * d;
             }
             row[iu] = (double)proj[(j * nv + iv) * nu + iu] * D / sqrt(r2);
@@ -722,6 +738,15 @@ void orc_fdk(const float *proj, int32_t n_views, int32_t nu, int32_t nv, const f
                 for (int64_t j = 0; j < n_views; ++j) {
                     double s[3], det[3], eu[3], ev[3], n[3], D, R;
                     view_frame(views + 12 * j, s, det, eu, ev, n, &D, &R);
+                    if (fan) {
+                        double w[3] = {det[0] - s[0], det[1] - s[1], det[2] - s[2]};
+                        double m[3] = {w[1] * eu[2] - w[2] * eu[1], w[2] * eu[0] - w[0] * eu[2],
+                                       w[0] * eu[1] - w[1] * eu[0]};
+                        double em = ev[0] * m[0] + ev[1] * m[1] + ev[2] * m[2];
+                        double b = ((x[0] - s[0]) * m[0] + (x[1] - s[1]) * m[1] + (x[2] - s[2]) * m[2]) / em;
+                        for (int a = 0; a < 3; ++a) s[a] += b * ev[a];
+                        R = -(s[0] * n[0] + s[1] * n[1] + s[2] * n[2]);
+                    }
                     double r[3] = {x[0] - s[0], x[1] - s[1], x[2] - s[2]};
                     double U = r[0] * n[0] + r[1] * n[1] + r[2] * n[2];
                     if (!(U > 0)) continue;

@@ -43,7 +43,8 @@ dgr_status check_trunc(const dgr_trunc *t) {
 
 dgr_status check_geometry(const dgr_geometry *g) {
     DGR_CHECK(g != nullptr, "geometry is null");
-    DGR_CHECK(g->kind == DGR_PARALLEL || g->kind == DGR_CONE, "geometry kind %d unknown", g->kind);
+    DGR_CHECK(g->kind == DGR_PARALLEL || g->kind == DGR_CONE || g->kind == DGR_FAN, "geometry kind %d unknown",
+              g->kind);
     DGR_CHECK(g->n_views >= 1 && g->nu >= 1 && g->nv >= 1, "geometry sizes must be >= 1");
     DGR_CHECK(g->nu <= 65536 && g->nv <= 65536 && g->n_views <= 65535,
               "geometry sizes too large (nu, nv <= 65536, n_views <= 65535)");

@@ -131,8 +131,9 @@ __device__ void ray64(const Geom64 &G, int j, int iu, int iv, double c[3], doubl
             d[a] = v[a];
             o[a] = pix;
         } else {
-            d[a] = pix - (double)v[a];
-            o[a] = v[a];
+            const double src = G.kind == DGR_FAN ? (double)v[a] + av * (double)v[9 + a] : (double)v[a];
+            d[a] = pix - src;
+            o[a] = src;
         }
     }
     const double nd = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);

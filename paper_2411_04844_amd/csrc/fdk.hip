@@ -4,7 +4,9 @@
 // caption; FDK is also its baseline row in Tab. 1) and reports PSNR
 // (App. C.1).  FDK here is the textbook Feldkamp algorithm for a full circular
 // cone-beam scan on a flat detector: cosine weighting, a Ram-Lak ramp filter
-// along each detector row, and a voxel-driven weighted backprojection.
+// along each detector row, and a voxel-driven weighted backprojection.  For a
+// stack of fan-beam slices (each row with its own source) the same three
+// steps, taken with the row's source, are 2-D fan-beam FBP of every slice.
 #include <algorithm>
 #include <cmath>
 
@@ -16,9 +18,12 @@ namespace {
 constexpr double kPi = 3.14159265358979323846;
 
 // Per-view frame: detector normal n (source side -> detector), D = (det - s).n,
-// R = -s.n (isocentre depth), e_u / |e_u|^2 and e_v / |e_v|^2.
+// R = -s.n (isocentre depth), e_u / |e_u|^2 and e_v / |e_v|^2.  Fan beam:
+// the row position of a point x is (x - s).m_n with m_n = m / (e_v.m),
+// m = (det - s) x e_u (zero if e_v lies in the fan plane), and the row's
+// source is s + b e_v; D is the same for every row.
 struct FdkView {
-    double s[3], det[3], n[3], eu_n[3], ev_n[3];
+    double s[3], det[3], n[3], eu_n[3], ev_n[3], ev[3], m_n[3];
     double D, R, tau;  // tau: detector pitch along u at the isocentre
 };
 
@@ -44,10 +49,15 @@ __global__ void fdk_frames(const float *__restrict__ views, int n_views, FdkView
     }
     const double uu = eu[0] * eu[0] + eu[1] * eu[1] + eu[2] * eu[2];
     const double vv = ev[0] * ev[0] + ev[1] * ev[1] + ev[2] * ev[2];
+    const double w[3] = {f.det[0] - f.s[0], f.det[1] - f.s[1], f.det[2] - f.s[2]};
+    const double m[3] = {w[1] * eu[2] - w[2] * eu[1], w[2] * eu[0] - w[0] * eu[2], w[0] * eu[1] - w[1] * eu[0]};
+    const double em = ev[0] * m[0] + ev[1] * m[1] + ev[2] * m[2];
     for (int a = 0; a < 3; ++a) {
         f.n[a] = n[a];
         f.eu_n[a] = eu[a] / uu;
         f.ev_n[a] = ev[a] / vv;
+        f.ev[a] = ev[a];
+        f.m_n[a] = em != 0.0 ? m[a] / em : 0.0;
     }
     f.D = D;
     f.R = -(f.s[0] * n[0] + f.s[1] * n[1] + f.s[2] * n[2]);
@@ -60,14 +70,16 @@ __global__ void fdk_frames(const float *__restrict__ views, int n_views, FdkView
 // The row and the sum are kept in binary64: the taps cancel strongly inside
 // a uniform object.  Only q is rounded to binary32.
 __global__ __launch_bounds__(256) void fdk_filter(const float *__restrict__ proj, const float *__restrict__ views,
-                                                  const FdkView *__restrict__ frames, int nu, int nv,
+                                                  const FdkView *__restrict__ frames, int nu, int nv, int fan,
                                                   float *__restrict__ q) {
     extern __shared__ double row[];
     const int iv = blockIdx.x, j = blockIdx.y;
     const FdkView &f = frames[j];
     const float *v = views + 12 * (int64_t)j;
     const float *src = proj + ((int64_t)j * nv + iv) * nu;
-    const double av = (double)iv - 0.5 * (nv - 1);
+    // fan beam: the row's source moves with the row, so the source-to-pixel
+    // vector has no e_v part
+    const double av = fan ? 0.0 : (double)iv - 0.5 * (nv - 1);
     for (int i = threadIdx.x; i < nu; i += 256) {
         const double au = (double)i - 0.5 * (nu - 1);
         double r2 = 0.0;
@@ -93,10 +105,11 @@ __global__ __launch_bounds__(256) void fdk_filter(const float *__restrict__ proj
 
 // Voxel-driven backprojection: f(x) = (dbeta/2) sum_j (R/U)^2 q_j(a, b) / ell,
 // U = (x - s).n, (a, b) the detector position of the ray s -> x (binary64
-// geometry), q bilinear and zero outside the detector.
+// geometry), q bilinear and zero outside the detector.  Fan beam: s is the
+// source of the (continuous) row b that holds x, and R = -s.n that row's.
 __global__ __launch_bounds__(256) void fdk_backproject(const float *__restrict__ q,
                                                        const FdkView *__restrict__ frames, int n_views,
-                                                       int nu, int nv, DevGrid g, double weight,
+                                                       int nu, int nv, int fan, DevGrid g, double weight,
                                                        float *__restrict__ V) {
     const int64_t total = (int64_t)g.nx * g.ny * g.nz;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
@@ -107,12 +120,19 @@ __global__ __launch_bounds__(256) void fdk_backproject(const float *__restrict__
         double acc = 0.0;
         for (int j = 0; j < n_views; ++j) {
             const FdkView &f = frames[j];
-            const double r[3] = {x[0] - f.s[0], x[1] - f.s[1], x[2] - f.s[2]};
+            double sv[3];
+            if (fan) {
+                const double b = (x[0] - f.s[0]) * f.m_n[0] + (x[1] - f.s[1]) * f.m_n[1] + (x[2] - f.s[2]) * f.m_n[2];
+                for (int a = 0; a < 3; ++a) sv[a] = f.s[a] + b * f.ev[a];
+            } else {
+                for (int a = 0; a < 3; ++a) sv[a] = f.s[a];
+            }
+            const double r[3] = {x[0] - sv[0], x[1] - sv[1], x[2] - sv[2]};
             const double U = r[0] * f.n[0] + r[1] * f.n[1] + r[2] * f.n[2];
             if (!(U > 0.0)) continue;
             const double t = f.D / U;
             double hit[3];
-            for (int a = 0; a < 3; ++a) hit[a] = f.s[a] + t * r[a] - f.det[a];
+            for (int a = 0; a < 3; ++a) hit[a] = sv[a] + t * r[a] - f.det[a];
             const double ap = hit[0] * f.eu_n[0] + hit[1] * f.eu_n[1] + hit[2] * f.eu_n[2] + 0.5 * (nu - 1);
             const double bp = hit[0] * f.ev_n[0] + hit[1] * f.ev_n[1] + hit[2] * f.ev_n[2] + 0.5 * (nv - 1);
             const double fa = floor(ap), fb = floor(bp);
@@ -128,7 +148,8 @@ __global__ __launch_bounds__(256) void fdk_backproject(const float *__restrict__
             const float q11 = (a1 && b1) ? qj[(int64_t)(ib + 1) * nu + ia + 1] : 0.0f;
             const float lo = fmaf(wa, q10 - q00, q00), hi = fmaf(wa, q11 - q01, q01);
             const double val = (double)fmaf(wb, hi - lo, lo);
-            const double m = f.R / U;
+            const double Rv = -(sv[0] * f.n[0] + sv[1] * f.n[1] + sv[2] * f.n[2]);
+            const double m = Rv / U;
             acc += m * m * val;
         }
         V[i] = (float)(acc * weight);
@@ -286,10 +307,10 @@ __global__ __launch_bounds__(256) void apply_scale(const double *__restrict__ pa
 
 unsigned red_blocks(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(kRedBlocks, (n + 255) / 256)); }
 
-dgr_status check_cone(const dgr_geometry *geom) {
+dgr_status check_fdk_geometry(const dgr_geometry *geom) {
     dgr_status s = check_geometry(geom);
     if (s != DGR_OK) return s;
-    DGR_CHECK(geom->kind == DGR_CONE, "FDK needs a cone-beam geometry");
+    DGR_CHECK(geom->kind == DGR_CONE || geom->kind == DGR_FAN, "FDK needs a cone-beam or fan-beam geometry");
     DGR_CHECK(geom->nu <= 8192, "FDK rows are staged in LDS as binary64: nu <= 8192");
     return DGR_OK;
 }
@@ -300,7 +321,7 @@ dgr_status check_cone(const dgr_geometry *geom) {
 using namespace dgr;
 
 extern "C" size_t dgr_fdk_workspace(const dgr_grid *grid, const dgr_geometry *geom) {
-    if (check_grid(grid) != DGR_OK || check_cone(geom) != DGR_OK) return 0;
+    if (check_grid(grid) != DGR_OK || check_fdk_geometry(geom) != DGR_OK) return 0;
     Carver c(nullptr);
     c.take<FdkView>(geom->n_views);
     c.take<float>((int64_t)geom->n_views * geom->nu * geom->nv);
@@ -311,7 +332,7 @@ extern "C" dgr_status dgr_fdk(const float *proj, const dgr_grid *grid, const dgr
                               float *volume, void *ws, size_t ws_bytes, void *stream) {
     dgr_status s;
     if ((s = check_grid(grid)) != DGR_OK) return s;
-    if ((s = check_cone(geom)) != DGR_OK) return s;
+    if ((s = check_fdk_geometry(geom)) != DGR_OK) return s;
     DGR_CHECK(proj && volume && ws, "null pointer argument");
     DGR_CHECK(std::isfinite(arc) && arc > 0.0f, "arc must be > 0");
     if (ws_bytes < dgr_fdk_workspace(grid, geom)) return fail(DGR_ERR_WORKSPACE, "workspace too small for FDK");
@@ -322,12 +343,12 @@ extern "C" dgr_status dgr_fdk(const float *proj, const dgr_grid *grid, const dgr
     fdk_frames<<<dim3((geom->n_views + 63) / 64), dim3(64), 0, st>>>(geom->views, geom->n_views, frames);
     DGR_LAUNCH_CHECK();
     fdk_filter<<<dim3(geom->nv, geom->n_views), dim3(256), sizeof(double) * geom->nu, st>>>(
-        proj, geom->views, frames, geom->nu, geom->nv, q);
+        proj, geom->views, frames, geom->nu, geom->nv, geom->kind == DGR_FAN, q);
     DGR_LAUNCH_CHECK();
     const int64_t nvox = (int64_t)grid->dims[0] * grid->dims[1] * grid->dims[2];
     const double weight = 0.5 * ((double)arc / geom->n_views) / (double)geom->length_scale;
     fdk_backproject<<<dim3((unsigned)std::min<int64_t>((nvox + 255) / 256, 65536)), dim3(256), 0, st>>>(
-        q, frames, geom->n_views, geom->nu, geom->nv, dev_grid(grid), weight, volume);
+        q, frames, geom->n_views, geom->nu, geom->nv, geom->kind == DGR_FAN, dev_grid(grid), weight, volume);
     DGR_LAUNCH_CHECK();
     return DGR_OK;
 }

@@ -92,6 +92,12 @@ inline DevGrid dev_grid(const dgr_grid *g) {
 // shadow lies in the bounding rectangle of its projected corners.  If a corner
 // cannot be projected (behind a cone source, or a ray parallel to the
 // detector) the whole detector is returned.  An empty rectangle has iu0 > iu1.
+// Fan beam: a point x belongs to the row whose fan plane holds it, row
+// position b = ((x - a).m)/(e_v.m) with m = (det - a) x e_u, and is projected
+// from that row's source a + b e_v.  When e_v is orthogonal to e_u and to
+// det - a this splits into a linear map along e_v and a perspective map of
+// the box's orthogonal projection onto the fan plane, so the corners still
+// bound the shadow; other views get the whole detector.
 __device__ inline void shadow_rect(int kind, const float *view, int nu, int nv, const DevGrid &g,
                                    const double ulo[3], const double uhi[3], int *iu0, int *iu1,
                                    int *iv0, int *iv1) {
@@ -110,17 +116,35 @@ __device__ inline void shadow_rect(int kind, const float *view, int nu, int nv, 
     const double det2 = uu * vv - uv * uv;
     double amin = 1e300, amax = -1e300, bmin = 1e300, bmax = -1e300;
     bool ok = det2 > 0.0;
+    double m[3] = {0.0, 0.0, 0.0}, em = 0.0;
+    if (kind == DGR_FAN && ok) {
+        const double w[3] = {D0[0] - A[0], D0[1] - A[1], D0[2] - A[2]};
+        m[0] = w[1] * eu[2] - w[2] * eu[1];
+        m[1] = w[2] * eu[0] - w[0] * eu[2];
+        m[2] = w[0] * eu[1] - w[1] * eu[0];
+        em = ev[0] * m[0] + ev[1] * m[1] + ev[2] * m[2];
+        const double ww = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+        const double ew = ev[0] * w[0] + ev[1] * w[1] + ev[2] * w[2];
+        // orthogonality to 1e-6 (binary32 views of an exact geometry are
+        // orthogonal to about 1e-7); the widening by one pixel absorbs the rest
+        ok = fabs(uv) <= 1e-6 * sqrt(uu * vv) && fabs(ew) <= 1e-6 * sqrt(ww * vv) && fabs(em) > 0.0;
+    }
     for (int c = 0; c < 8 && ok; ++c) {
-        double X[3], dir[3];
+        double X[3], dir[3], src[3];
         for (int a = 0; a < 3; ++a) {
             const double u = ((c >> a) & 1) ? uhi[a] : ulo[a];
             X[a] = (double)g.lo[a] + (u + 0.5) / (double)g.inv_h[a];
-            dir[a] = kind == DGR_PARALLEL ? A[a] : X[a] - A[a];
+        }
+        const double brow = kind == DGR_FAN
+            ? ((X[0] - A[0]) * m[0] + (X[1] - A[1]) * m[1] + (X[2] - A[2]) * m[2]) / em : 0.0;
+        for (int a = 0; a < 3; ++a) {
+            src[a] = A[a] + brow * ev[a];
+            dir[a] = kind == DGR_PARALLEL ? A[a] : X[a] - src[a];
         }
         const double den = n[0] * dir[0] + n[1] * dir[1] + n[2] * dir[2];
         if (!(fabs(den) > 1e-300)) { ok = false; break; }
         const double t = (n[0] * (D0[0] - X[0]) + n[1] * (D0[1] - X[1]) + n[2] * (D0[2] - X[2])) / den;
-        if (kind == DGR_CONE && !(t > -1.0)) { ok = false; break; }  // corner behind the source
+        if (kind != DGR_PARALLEL && !(t > -1.0)) { ok = false; break; }  // corner behind the source
         double P[3];
         for (int a = 0; a < 3; ++a) P[a] = X[a] + t * dir[a] - D0[a];
         const double pu = P[0] * eu[0] + P[1] * eu[1] + P[2] * eu[2];

@@ -108,7 +108,8 @@ constexpr double kMaxK = 4194304.0;                 // |k| limit (2^22) for fixe
 
 
 // Unit direction and anchor of the ray through pixel (iu, iv) of view j, in
-// binary64.  1/|d| comes from the hardware estimate refined by two Newton steps.
+// binary64 (fan beam: the source of row iv is a + av e_v).  1/|d| comes from
+// the hardware estimate refined by two Newton steps.
 __device__ __forceinline__ void ray_geom(const GeomDev &G, const DevGrid &g, int j, int iu, int iv,
                                          Ray &r) {
     const float *v = G.views + 12 * (int64_t)j;
@@ -122,8 +123,9 @@ __device__ __forceinline__ void ray_geom(const GeomDev &G, const DevGrid &g, int
             d[a] = (double)v[a];
             o[a] = pix;
         } else {
-            d[a] = pix - (double)v[a];
-            o[a] = (double)v[a];
+            const double src = G.kind == DGR_FAN ? fma(av, (double)v[9 + a], (double)v[a]) : (double)v[a];
+            d[a] = pix - src;
+            o[a] = src;
         }
     }
     const double n2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];

@@ -57,7 +57,7 @@ def cube_grid(D: int) -> GridSpec:
 class Geometry:
     """Acquisition geometry; step and length_scale are stored rounded to
     binary32 (the ABI's precision), views are binary32."""
-    kind: int          # 0 parallel, 1 cone
+    kind: int          # 0 parallel, 1 cone, 2 fan (a stack of fan-beam rows)
     views: np.ndarray  # float32 [n_views, 12]
     nu: int
     nv: int
@@ -142,6 +142,41 @@ def cone_geometry(n_views: int, nu: int, nv: int, pitch: float, dso: float, dsd:
     return Geometry(1, v.astype(np.float32), nu, nv, step, length_scale)
 
 
+def fan_geometry(n_views: int, nu: int, nv: int, pitch_u: float, pitch_v: float, dso: float,
+                 dsd: float, step: float, arc: float = 2 * math.pi, start: float = 0.0,
+                 length_scale: float = MM_PER_UNIT) -> Geometry:
+    """A stack of nv fan-beam slices about z with a flat (line) detector per
+    slice, world units: view j at t = start + arc * j / n_views.
+
+    Source of the central row at dso (cos t, sin t, 0), detector centre at
+    -(dsd - dso)(cos t, sin t, 0); e_u = pitch_u (-sin t, cos t, 0) and
+    e_v = pitch_v (0, 0, 1).  Row iv sits at height (iv - (nv-1)/2) pitch_v,
+    its source at the same height.
+    """
+    v = np.zeros((n_views, 12), np.float64)
+    for j in range(n_views):
+        t = start + arc * j / n_views
+        c, s = math.cos(t), math.sin(t)
+        v[j, 0:3] = (dso * c, dso * s, 0.0)
+        v[j, 3:6] = (-(dsd - dso) * c, -(dsd - dso) * s, 0.0)
+        v[j, 6:9] = (-s * pitch_u, c * pitch_u, 0.0)
+        v[j, 9:12] = (0.0, 0.0, pitch_v)
+    return Geometry(2, v.astype(np.float32), nu, nv, step, length_scale)
+
+
+def fan_workload(D: int, n_views: int, n_det: int, arc: float = 2 * math.pi, start: float = 0.0,
+                 dso_mm: float = 595.0, dsd_mm: float = 1085.6) -> Geometry:
+    """Fan beam over the 256 mm cube: one detector row per slice (pitch = the
+    slice thickness, so rows sit on voxel centres in z), n_det columns that
+    span 1.5 D voxels at the isocentre (the cube's diagonal is 1.41 D), march
+    step 0.5 voxel.  Distances follow a clinical fan-beam scanner
+    (source-isocentre 595 mm, source-detector 1085.6 mm)."""
+    h = 2.0 / D
+    mag = dsd_mm / dso_mm
+    return fan_geometry(n_views, n_det, D, mag * h * 1.5 * D / n_det, h, dso_mm / MM_PER_UNIT,
+                        dsd_mm / MM_PER_UNIT, 0.5 * h, arc, start)
+
+
 def cone_workload(D: int, n_views: int, n_det: int, pitch_mm: float, arc=2 * math.pi,
                   dso_mm: float = 1000.0, dsd_mm: float = 1500.0) -> Geometry:
     """Cone geometry in world units for a 256 mm cube, march step 0.5 voxel."""
@@ -206,8 +241,12 @@ def _ray_dirs(geom: Geometry, views_idx, device, torch):
     if geom.kind == 0:
         d = v[:, None, None, 0:3].expand_as(pix)
         o = pix
-    else:
+    elif geom.kind == 1:
         o = v[:, None, None, 0:3].expand_as(pix)
+        d = pix - o
+    else:  # fan: each row's source sits at the row's height
+        o = v[:, None, None, 0:3] + iv[None, :, None, None] * v[:, None, None, 9:12]
+        o = o.expand_as(pix)
         d = pix - o
     d = d / torch.linalg.norm(d, dim=-1, keepdim=True)
     return o, d

@@ -9,6 +9,7 @@ backward needs only the parameters and dL/dV.
 """
 from __future__ import annotations
 
+import math
 from dataclasses import dataclass, field
 
 import torch
@@ -226,11 +227,12 @@ class DensityControl:
 # workload builders
 # --------------------------------------------------------------------------
 def cone_problem(D=256, n=100_000, n_views=360, n_det=512, pitch_mm=0.8, s_lo=0.004, s_hi=0.03,
-                 seeds=(2001, 2002, 2003), device="cuda", ratio_max=None) -> Problem:
+                 seeds=(2001, 2002, 2003), device="cuda", ratio_max=None, geom=None) -> Problem:
     """Synthetic cone-beam workload: seeded Gaussians, ellipsoid phantom with
-    analytic projections plus 1 % Gaussian noise as the target."""
+    analytic projections plus 1 % Gaussian noise as the target.  `geom`
+    replaces the cone geometry (e.g. a fan-beam slice stack)."""
     grid = inputs.cube_grid(D)
-    geom = inputs.cone_workload(D, n_views, n_det, pitch_mm)
+    geom = geom if geom is not None else inputs.cone_workload(D, n_views, n_det, pitch_mm)
     G = inputs.gaussians(n, seeds[0], s_lo, s_hi, ratio_max=ratio_max)
     ph = inputs.ellipsoid_phantom(seeds[1])
     y = inputs.phantom_projections(ph, geom, device=device)
@@ -258,12 +260,29 @@ def sparse_view_problem(D=256, n_views=25, n_det=512, pitch_mm=0.8, seeds=(3002,
     return Problem(grid, geom, views, y, {}), gt
 
 
-def fdk_init(prob: Problem, n=50_000, seed=3004, scale_vox=1.5, thresh=0.1):
-    """FDK volume -> n Gaussians drawn where it exceeds thresh * max, isotropic
-    scale of scale_vox voxels, density = FDK value times the least-squares
-    scale that best fits the projections.  Returns the parameter dict."""
+def fan_problem(D=256, n_views=60, n_det=384, arc=2 * math.pi, start=0.0, seeds=(3002, 3003),
+                device="cuda", noise_frac=0.01):
+    """Fan-beam workload: a stack of D fan-beam slices (one detector row per
+    slice), n_views over `arc` radians from `start`; with arc = pi/2 it is the
+    90-degree limited-angle setting.  The same phantom recipe and noise as the
+    cone-beam workloads; returns (Problem, ground-truth volume)."""
+    grid = inputs.cube_grid(D)
+    geom = inputs.fan_workload(D, n_views, n_det, arc=arc, start=start)
+    ph = inputs.ellipsoid_phantom(seeds[0])
+    y = inputs.add_noise(inputs.phantom_projections(ph, geom, device=device), seeds[1],
+                         noise_frac).contiguous()
+    gt = inputs.phantom_volume(ph, grid, device=device).to(torch.float32).contiguous()
+    views = torch.as_tensor(geom.views).to(device).contiguous()
+    return Problem(grid, geom, views, y, {}), gt
+
+
+def fdk_init(prob: Problem, n=50_000, seed=3004, scale_vox=1.5, thresh=0.1, arc=2 * math.pi):
+    """FDK volume (fan-beam FBP for a fan-beam problem) -> n Gaussians drawn
+    where it exceeds thresh * max, isotropic scale of scale_vox voxels,
+    density = FDK value times the least-squares scale that best fits the
+    projections.  Returns the parameter dict."""
     dev = prob.target.device
-    f = native.dgr_fdk(prob.target, prob.grid, prob.geom, prob.views)
+    f = native.dgr_fdk(prob.target, prob.grid, prob.geom, prob.views, arc=arc)
     g = torch.Generator(device="cpu").manual_seed(seed)
     uni = torch.rand((n, 4), generator=g, dtype=torch.float32).to(dev)
     h = 1.0 / prob.grid.inv_h[0]
