@@ -249,6 +249,27 @@ __device__ __forceinline__ void march_span(const float *vol, int sy, int sz, con
     }
 }
 
+// march_span over the LDS box: the tap index (cells within the box, so every
+// term is below 2^24) takes two 24-bit multiply-adds per sample instead of
+// two full-width multiplies.
+__device__ __forceinline__ void march_box(const float *box, int sy, int sz, const int o[3], const Ray &r,
+                                          int a, int e, float &acc) {
+    long long ux = r.U[0] + (long long)a * r.DU[0] - ((long long)o[0] << 32);
+    long long uy = r.U[1] + (long long)a * r.DU[1] - ((long long)o[1] << 32);
+    long long uz = r.U[2] + (long long)a * r.DU[2] - ((long long)o[2] << 32);
+    for (int k = a; k <= e; ++k) {
+        const int lx = (int)(ux >> 32), ly = (int)(uy >> 32), lz = (int)(uz >> 32);
+        const float wx = (float)(unsigned)ux * kInv32;
+        const float wy = (float)(unsigned)uy * kInv32;
+        const float wz = (float)(unsigned)uz * kInv32;
+        const unsigned idx = __umul24((unsigned)lz, (unsigned)sz) + __umul24((unsigned)ly, (unsigned)sy) + (unsigned)lx;
+        acc += trilinear(box + idx, sy, sz, wx, wy, wz);
+        ux += r.DU[0];
+        uy += r.DU[1];
+        uz += r.DU[2];
+    }
+}
+
 __device__ __forceinline__ int wave_min(int v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
@@ -272,16 +293,17 @@ __device__ __forceinline__ float wave_sum(float v) {
 // the work-group finds the box of cells its samples touch (sample positions
 // are affine in k, so the floors at the two ends of each ray's span bound
 // them), copies that box of the padded volume into LDS with coalesced rows,
-// and reads the eight taps of every sample from LDS.  Rays of a bundle are
-// nearly parallel, so the box stays small (about 16 x 16 x 13 voxels for an
-// 8-voxel chunk at 45 degrees); a chunk whose box exceeds the LDS box reads
-// its taps from the padded copy instead.  Work-groups are numbered so each
-// XCD (which receives every 8th dispatched work-group) runs a contiguous range
-// of bundles.  mode 0: write P_hat; mode 1: fused L1 (loss partial per
-// work-group + dproj).
-constexpr int kBun = 16;                     // bundle edge (pixels)
-constexpr int kLX = 20, kLY = 20, kLZ = 14;  // LDS box (voxels, 22 KB)
-constexpr int kFwdChunk = 16;                // samples per chunk
+// and reads the eight taps of every sample from LDS.  The box is stored dense
+// (x fastest, its own extents as strides), so any shape up to kBoxCap cells
+// fits: rays of a cone-beam bundle are nearly parallel (about 16 x 16 x 13
+// cells for an 8-voxel chunk at 45 degrees), a fan-beam bundle's 16 rows
+// span 16 slices.  A chunk whose box exceeds kBoxCap reads its taps from the
+// padded copy instead.  Work-groups are numbered so each XCD (which receives
+// every 8th dispatched work-group) runs a contiguous range of bundles.
+// mode 0: write P_hat; mode 1: fused L1 (loss partial per work-group + dproj).
+constexpr int kBun = 16;         // bundle edge (pixels)
+constexpr int kBoxCap = 5600;    // LDS box (cells, 22 KB)
+constexpr int kFwdChunk = 16;    // samples per chunk
 
 __device__ __forceinline__ void block_bounds(int v[6], int (*red)[8], int wave, int lane) {
 #pragma unroll
@@ -304,7 +326,7 @@ __global__ __launch_bounds__(256) void project_bundles(const float *__restrict__
                                                        const float *__restrict__ target,
                                                        float *__restrict__ out, float inv_m,
                                                        float *__restrict__ partial) {
-    __shared__ float box[kLX * kLY * kLZ];
+    __shared__ float box[kBoxCap];
     __shared__ int red[2][4][8];
     const int64_t per_xcd = (nb + kXcd - 1) / kXcd;
     const int64_t b = (int64_t)(blockIdx.x % kXcd) * per_xcd + blockIdx.x / kXcd;
@@ -345,17 +367,42 @@ __global__ __launch_bounds__(256) void project_bundles(const float *__restrict__
             }
         }
         block_bounds(bb, red[it & 1], wave, lane);  // alternate buffers: no reuse race
+        // No ray of the bundle has a sample in this chunk (the union of the
+        // rays' sample ranges can have gaps): the bounds are still the
+        // sentinels.  The test is uniform over the work-group.
+        if (bb[0] > bb[3]) continue;
         const int o[3] = {bb[0], bb[1], bb[2]};
         const int nx = bb[3] - bb[0] + 2, ny = bb[4] - bb[1] + 2, nz = bb[5] - bb[2] + 2;
-        if (nx <= kLX && ny <= kLY && nz <= kLZ) {
-            // taps of the chunk: padded voxels o .. o + n - 1, inside the padded copy
+        if ((int64_t)nx * ny * nz <= kBoxCap) {
+            // taps of the chunk: padded voxels o .. o + n - 1, inside the padded
+            // copy.  Box element q is cell (q mod nx, (q / nx) mod ny,
+            // q / (nx ny)); the quotients come from binary32 reciprocals, exact
+            // here: (q + 1/2) / n_a lies at least 1/(2 n_a) from an integer and
+            // its rounding error is below (q + 1/2) / n_a * 2^-23, smaller for
+            // q < 2^22.  Each thread issues kStage loads before its first LDS
+            // write, so the loads overlap.
             const int n = nx * ny * nz;
-            for (int q = t; q < n; q += 256) {
-                const int lx = q % nx, rq = q / nx, ly = rq % ny, lz = rq / ny;
-                box[(lz * kLY + ly) * kLX + lx] = vp[((int64_t)(o[2] + lz) * p.py + (o[1] + ly)) * p.px + o[0] + lx];
+            const float inx = 1.0f / (float)nx, iny = 1.0f / (float)ny;
+            const float *src = vp + ((int64_t)o[2] * p.py + o[1]) * p.px + o[0];
+            constexpr int kStage = 4;
+            for (int q0 = t; q0 < n; q0 += 256 * kStage) {
+                float v[kStage];
+#pragma unroll
+                for (int u = 0; u < kStage; ++u) {
+                    const int q = q0 + u * 256;
+                    if (q < n) {
+                        const int rq = (int)(((float)q + 0.5f) * inx);
+                        const int lz = (int)(((float)rq + 0.5f) * iny);
+                        const int lx = q - rq * nx, ly = rq - lz * ny;
+                        v[u] = src[(int64_t)lz * p.plane + ly * p.px + lx];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kStage; ++u)
+                    if (q0 + u * 256 < n) box[q0 + u * 256] = v[u];
             }
             __syncthreads();
-            if (has) march_span(box, kLX, kLX * kLY, o, r, a, e, acc);
+            if (has) march_box(box, nx, nx * ny, o, r, a, e, acc);
             __syncthreads();
         } else if (has) {
             const int o0[3] = {0, 0, 0};

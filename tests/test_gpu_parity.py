@@ -243,6 +243,33 @@ def test_backproject_parity_and_adjoint(kind):
     assert abs(lhs - rhs) <= TOL * np.linalg.norm(Ax) * np.linalg.norm(g)
 
 
+def test_project_rays_with_disjoint_sample_ranges():
+    """Two rays of one pixel bundle whose sample ranges are far apart
+    ([-149, -50] and [50, 149]): the chunks between them hold no sample of
+    any ray of the bundle and must be skipped."""
+    say("project disjoint ranges")
+    grid = inputs.GridSpec((160, 4, 4), (-5.0, -0.125, -0.125), (16.0, 16.0, 16.0))
+    a, h = 0.1, 1.0 / 16
+    v = np.zeros((1, 12), np.float64)
+    v[0, 0:3] = (math.cos(a), math.sin(a), 0.0)
+    v[0, 6:9] = (-math.sin(a) * 10 * h, math.cos(a) * 10 * h, 0.0)
+    v[0, 9:12] = (0.0, 0.0, h)
+    geom = inputs.Geometry(0, v.astype(np.float32), 2, 1, h / 2, 1.0)
+    V = np.random.default_rng(93).uniform(size=grid.shape).astype(np.float32)
+    views = dev(geom.views)
+    got = native.dgr_project(dev(V), grid, geom, views).cpu().numpy()
+    want = oracle.project(V.astype(np.float64), grid.dims, grid.lo, grid.inv_h, geom.kind, geom.views,
+                          geom.nu, geom.nv, geom.step, geom.length_scale)
+    assert np.all(want > 0)
+    say("project disjoint ranges rel_l2", rel_l2(got, want))
+    assert rel_l2(got, want) < TOL
+    g = np.array([[[1.0, -2.0]]], np.float32)
+    gotb = native.dgr_backproject(dev(g), grid, geom, views).cpu().numpy()
+    wantb = oracle.backproject(g.astype(np.float64), grid.dims, grid.lo, grid.inv_h, geom.kind, geom.views,
+                               geom.nu, geom.nv, geom.step, geom.length_scale)
+    assert rel_l2(gotb, wantb) < TOL
+
+
 # --------------------------------------------------------------------------
 # voxelization backward and Adam
 # --------------------------------------------------------------------------
