@@ -270,6 +270,41 @@ def test_project_rays_with_disjoint_sample_ranges():
     assert rel_l2(gotb, wantb) < TOL
 
 
+def test_projector_degenerate_cases():
+    """Rays that all miss the grid give exact zeros both ways; a one-pixel
+    detector matches the oracle; a zero gradient (max |g| = 0, the
+    fixed-point scale's degenerate case) backprojects to exact zeros."""
+    say("project degenerate")
+    grid = GRIDS["ragged"]
+    V = np.random.default_rng(94).uniform(size=grid.shape).astype(np.float32)
+    v = np.zeros((2, 12), np.float32)
+    v[:, 0:3] = (1.0, 0.0, 0.0)            # along x
+    v[:, 3:6] = (0.0, 5.0, 0.0)            # detector far beside the grid
+    v[:, 6:9] = (0.0, 0.05, 0.0)
+    v[:, 9:12] = (0.0, 0.0, 0.05)
+    miss = inputs.Geometry(0, v, 7, 5, 0.03, 1.0)
+    views = dev(miss.views)
+    P = native.dgr_project(dev(V), grid, miss, views).cpu().numpy()
+    assert np.all(P == 0.0)
+    g = np.random.default_rng(95).normal(size=(2, 5, 7)).astype(np.float32)
+    B = native.dgr_backproject(dev(g), grid, miss, views).cpu().numpy()
+    assert np.all(B == 0.0)
+    one = inputs.cone_geometry(3, 1, 1, 0.05, 3.0, 4.5, 0.03, arc=2.0, length_scale=1.0)
+    got = native.dgr_project(dev(V), grid, one, dev(one.views)).cpu().numpy()
+    want = oracle.project(V.astype(np.float64), grid.dims, grid.lo, grid.inv_h, one.kind, one.views,
+                          one.nu, one.nv, one.step, one.length_scale)
+    assert np.all(want > 0) and rel_l2(got, want) < TOL
+    gone = np.array([[[0.7]], [[-1.3]], [[2.1]]], np.float32)
+    gotb = native.dgr_backproject(dev(gone), grid, one, dev(one.views)).cpu().numpy()
+    wantb = oracle.backproject(gone.astype(np.float64), grid.dims, grid.lo, grid.inv_h, one.kind, one.views,
+                               one.nu, one.nv, one.step, one.length_scale)
+    assert rel_l2(gotb, wantb) < TOL
+    cone = inputs.cone_geometry(4, 9, 7, 0.1, 3.0, 4.5, 0.03, length_scale=1.0)
+    Z = native.dgr_backproject(torch.zeros((4, 7, 9), device="cuda"), grid, cone,
+                               dev(cone.views)).cpu().numpy()
+    assert np.all(Z == 0.0)
+
+
 # --------------------------------------------------------------------------
 # voxelization backward and Adam
 # --------------------------------------------------------------------------
