@@ -31,9 +31,11 @@
 //                fragments are loaded straight from memory (8 contiguous
 //                channels per lane).  The data gradient is the same kernel
 //                with transposed, tap-reversed weights.
-//   conv3_wgrad  dW[t] = dY^T shift_t(X): K = voxels, so 64-voxel tiles of
-//                both operands are transposed through LDS; split over voxel
-//                chunks into binary32 partials summed in a fixed order.
+//   conv3_wgrad  dW[t] = dY^T shift_t(X): K = voxels, so 128-voxel tiles of
+//                both operands are transposed through LDS, three taps (the
+//                three x shifts) per work-group sharing the dY tile; split
+//                over voxel chunks into binary32 partials summed in a fixed
+//                order.
 //   conv1_*      the 1-channel first layer on the VALU (K = 27).
 //   pooling, upsampling (with the ReLU masks of the backward fused in), the
 //   1x1 head and the loss are elementwise VALU kernels.
@@ -147,22 +149,39 @@ __global__ __launch_bounds__(256) void conv3_mfma(const u16 *__restrict__ x, int
 }
 
 // ---- weight gradient ------------------------------------------------------------
-// Grid: x = 27 taps x (cout / 32) x (cin / 32) tiles, y = voxel chunks.  Each
-// work-group accumulates dW[t][co0 .. co0+31][ci0 .. ci0+31] over its chunk:
-// per 128-voxel step it stages dY[v][co] and X[v + t][ci] transposed in LDS
-// ([channel][voxel], so the K = voxel slice of a lane is contiguous); wave w
-// owns the 16x16 sub-tile (co0 + 16 (w / 2), ci0 + 16 (w % 2)) and issues 4
-// MFMAs per step.  Loader threads 0..127 stage dY, 128..255 stage X: each
-// takes 8 channels of 4 consecutive voxels and writes, per channel, the 4
-// voxels as one 64-bit LDS word.
+// Grid: x = 9 (dz, dy) tap rows x (cout / 32) x (cin / 32) tiles, y = voxel
+// chunks.  Each work-group accumulates dW[t][co0 .. co0+31][ci0 .. ci0+31]
+// for the three taps t = (dz, dy, dx = -1, 0, 1) of its row over its chunk:
+// per 128-voxel step it stages dY[v][co] once and X[v + (dx, dy, dz)][ci]
+// for the three dx, all transposed in LDS ([channel][voxel], so the K =
+// voxel slice of a lane is contiguous and 16-byte aligned); wave w owns the
+// 16x16 sub-tile (co0 + 16 (w / 2), ci0 + 16 (w % 2)) of each tap and issues
+// 12 MFMAs per step, reading each dY fragment once for the three taps.
+// Loader threads 0..127 stage dY, 128..255 stage X: each takes 8 channels of
+// 4 consecutive voxels and writes, per channel, the 4 voxels as one 64-bit
+// LDS word (for X, once per dx; the three loads of neighbouring voxels
+// share cache lines).
 constexpr int kWgStep = 128;
 constexpr int kWgPitch = kWgStep + 8;  // u16 per LDS row (272 bytes, 16-byte aligned)
+
+__device__ __forceinline__ void store_transposed(u16 *dst, int c8, int vg, const u32x4 (&q)[4]) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int sh = (j & 1) * 16;
+        const unsigned long long w =
+            (unsigned long long)((q[0][j >> 1] >> sh) & 0xffffu) |
+            ((unsigned long long)((q[1][j >> 1] >> sh) & 0xffffu) << 16) |
+            ((unsigned long long)((q[2][j >> 1] >> sh) & 0xffffu) << 32) |
+            ((unsigned long long)((q[3][j >> 1] >> sh) & 0xffffu) << 48);
+        *reinterpret_cast<unsigned long long *>(dst + (c8 + j) * kWgPitch + vg) = w;
+    }
+}
 
 __global__ __launch_bounds__(256) void conv3_wgrad(const u16 *__restrict__ x, int xs, Vol d, int cin,
                                                    const u16 *__restrict__ dy, int dys, int cout,
                                                    int64_t chunk, float *__restrict__ part) {
-    __shared__ __attribute__((aligned(16))) u16 At[32 * kWgPitch];  // [co][v]
-    __shared__ __attribute__((aligned(16))) u16 Bt[32 * kWgPitch];  // [ci][v]
+    __shared__ __attribute__((aligned(16))) u16 At[32 * kWgPitch];      // [co][v]
+    __shared__ __attribute__((aligned(16))) u16 Bt[3][32 * kWgPitch];   // [dx][ci][v]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, g = lane >> 4;
     const int n_ci = cin / 32, n_co = cout / 32;
@@ -170,61 +189,73 @@ __global__ __launch_bounds__(256) void conv3_wgrad(const u16 *__restrict__ x, in
     const int ib = tile % n_ci;
     tile /= n_ci;
     const int cb = tile % n_co;
-    const int t = tile / n_co;
-    const int dz = t / 9 - 1, dyy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+    const int trow = tile / n_co;  // (dz + 1) * 3 + (dy + 1)
+    const int dz = trow / 3 - 1, dyy = trow % 3 - 1;
     const int64_t v_begin = (int64_t)blockIdx.y * chunk;
     const int64_t v_end = min(d.V, v_begin + chunk);
     const int msub = (wave >> 1) * 16, nsub = (wave & 1) * 16;
-    f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    f32x4 acc[3];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) acc[s] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     const bool is_x = tid >= 128;
     const int lt = tid & 127;
     const int vg = (lt >> 2) * 4, c8 = (lt & 3) * 8;  // voxels vg..vg+3 of the step, channels c8..c8+7
-    u16 *dst = is_x ? Bt : At;
     for (int64_t v0 = v_begin; v0 < v_end; v0 += kWgStep) {
-        u32x4 q[4];
+        if (!is_x) {
+            u32x4 q[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            q[i] = u32x4{0u, 0u, 0u, 0u};
-            const int64_t v = v0 + vg + i;
-            if (v < v_end) {
-                if (!is_x) {
-                    q[i] = *reinterpret_cast<const u32x4 *>(dy + v * dys + cb * 32 + c8);
-                } else {
+            for (int i = 0; i < 4; ++i) {
+                const int64_t v = v0 + vg + i;
+                q[i] = v < v_end ? *reinterpret_cast<const u32x4 *>(dy + v * dys + cb * 32 + c8)
+                                 : u32x4{0u, 0u, 0u, 0u};
+            }
+            store_transposed(At, c8, vg, q);
+        } else {
+            u32x4 q[3][4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int64_t v = v0 + vg + i;
+#pragma unroll
+                for (int s = 0; s < 3; ++s) q[s][i] = u32x4{0u, 0u, 0u, 0u};
+                if (v < v_end) {
                     int px, py, pz;
                     vox_coords(d, v, &px, &py, &pz);
-                    const int xx = px + dx, yy = py + dyy, zz = pz + dz;
-                    if (xx >= 0 && yy >= 0 && zz >= 0 && xx < d.nx && yy < d.ny && zz < d.nz) {
-                        const int64_t vn = ((int64_t)zz * d.ny + yy) * d.nx + xx;
-                        q[i] = *reinterpret_cast<const u32x4 *>(x + vn * xs + ib * 32 + c8);
+                    const int yy = py + dyy, zz = pz + dz;
+                    if (yy >= 0 && zz >= 0 && yy < d.ny && zz < d.nz) {
+                        const u16 *row = x + (((int64_t)zz * d.ny + yy) * d.nx) * xs + ib * 32 + c8;
+#pragma unroll
+                        for (int s = 0; s < 3; ++s) {
+                            const int xx = px + s - 1;
+                            if (xx >= 0 && xx < d.nx)
+                                q[s][i] = *reinterpret_cast<const u32x4 *>(row + (int64_t)xx * xs);
+                        }
                     }
                 }
             }
-        }
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int sh = (j & 1) * 16;
-            const unsigned long long w =
-                (unsigned long long)((q[0][j >> 1] >> sh) & 0xffffu) |
-                ((unsigned long long)((q[1][j >> 1] >> sh) & 0xffffu) << 16) |
-                ((unsigned long long)((q[2][j >> 1] >> sh) & 0xffffu) << 32) |
-                ((unsigned long long)((q[3][j >> 1] >> sh) & 0xffffu) << 48);
-            *reinterpret_cast<unsigned long long *>(dst + (c8 + j) * kWgPitch + vg) = w;
+            for (int s = 0; s < 3; ++s) store_transposed(Bt[s], c8, vg, q[s]);
         }
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < kWgStep; kk += 32) {
             const bf16x8 a = *reinterpret_cast<const bf16x8 *>(At + (msub + r) * kWgPitch + kk + 8 * g);
-            const bf16x8 b = *reinterpret_cast<const bf16x8 *>(Bt + (nsub + r) * kWgPitch + kk + 8 * g);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+#pragma unroll
+            for (int s = 0; s < 3; ++s) {
+                const bf16x8 b = *reinterpret_cast<const bf16x8 *>(Bt[s] + (nsub + r) * kWgPitch + kk + 8 * g);
+                acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[s], 0, 0, 0);
+            }
         }
         __syncthreads();
     }
-    // lane holds D[4 g + i][r]: co = cb*32 + msub + 4g + i, ci = ib*32 + nsub + r
-    float *out = part + ((int64_t)blockIdx.y * 27 + t) * cout * cin;
+    // lane holds D[4 g + i][r] of each tap: co = cb*32 + msub + 4g + i, ci = ib*32 + nsub + r
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int co = cb * 32 + msub + 4 * g + i, ci = ib * 32 + nsub + r;
-        out[(int64_t)co * cin + ci] = acc[i];
+    for (int s = 0; s < 3; ++s) {
+        float *out = part + ((int64_t)blockIdx.y * 27 + trow * 3 + s) * cout * cin;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int co = cb * 32 + msub + 4 * g + i, ci = ib * 32 + nsub + r;
+            out[(int64_t)co * cin + ci] = acc[s][i];
+        }
     }
 }
 
@@ -714,7 +745,7 @@ dgr_status launch_wgrad(const u16 *x, int xs, const Vol &d, int cin, const u16 *
                         float *dW, float *db, hipStream_t st) {
     const int nc = wgrad_chunks(d.V);
     const int64_t chunk = (d.V + nc - 1) / nc;
-    const dim3 grid((unsigned)(27 * (cout / 32) * (cin / 32)), (unsigned)nc);
+    const dim3 grid((unsigned)(9 * (cout / 32) * (cin / 32)), (unsigned)nc);
     conv3_wgrad<<<grid, dim3(256), 0, st>>>(x, xs, d, cin, dy, cout, cout, chunk, part);
     DGR_LAUNCH_CHECK();
     const int64_t n = 27LL * cout * cin;
