@@ -189,8 +189,8 @@ dgr_status dgr_adam(float *param, const float *grad, float *m, float *v, int64_t
  * With a DGR_FAN geometry the same steps use each row's own source, which
  * makes it slice-by-slice fan-beam FBP: the cosine weight sees only the
  * in-row offset, and a voxel is read from the row whose fan plane holds it,
- * row position ((x - a).m)/(e_v.m) with m = (det - a) x e_u, linear between
- * rows.  proj [n_views][nv][nu] -> volume [nz][ny][nx] (overwritten).  geom
+ * row position ((x - a).m)/(e_v.m) with m = (det - a) x e_u (e_v must not
+ * lie in the fan plane), linear between rows.  proj [n_views][nv][nu] -> volume [nz][ny][nx] (overwritten).  geom
  * must be DGR_CONE or DGR_FAN with nu <= 8192 (a filtered row is staged in
  * LDS in binary64).  Returns DGR_ERR_INVALID_ARG otherwise; all pointers are
  * DEVICE pointers. */

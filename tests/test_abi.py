@@ -93,3 +93,21 @@ def test_project_workspace_covers_padded_volume():
     geom = native.DgrGeometry(1, 3, 17, 9, 0x10000, 0.01, 1.0)
     ws = L.dgr_project_workspace(ctypes.byref(g), ctypes.byref(geom))
     assert ws >= 44 * 34 * 24 * 4
+
+
+def test_geometry_kinds_on_the_host():
+    """Fan beam is a geometry of every projector entry point and of FDK;
+    FDK refuses a parallel beam; unknown kinds are refused everywhere."""
+    L = native.lib()
+    g = _grid()
+    fan = native.DgrGeometry(2, 3, 17, 9, 0x10000, 0.01, 1.0)
+    par = native.DgrGeometry(0, 3, 17, 9, 0x10000, 0.01, 1.0)
+    bad = native.DgrGeometry(3, 3, 17, 9, 0x10000, 0.01, 1.0)
+    assert L.dgr_project_workspace(ctypes.byref(g), ctypes.byref(fan)) > 0
+    assert L.dgr_fdk_workspace(ctypes.byref(g), ctypes.byref(fan)) > 0
+    assert L.dgr_fdk_workspace(ctypes.byref(g), ctypes.byref(par)) == 0
+    assert L.dgr_project_workspace(ctypes.byref(g), ctypes.byref(bad)) == 0
+    fake = ctypes.c_void_p(0x10000)
+    assert L.dgr_fdk(fake, ctypes.byref(g), ctypes.byref(par), 6.28, fake, fake, 1 << 30, None) == 1
+    assert b"cone-beam or fan-beam" in L.dgr_last_error()
+    assert L.dgr_backproject(fake, ctypes.byref(g), ctypes.byref(bad), fake, fake, 1 << 30, None) == 1
