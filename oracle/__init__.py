@@ -100,6 +100,8 @@ def lib():
         L.orc_backproject.restype = None
         L.orc_project_siddon.argtypes = [P, P, P, P, i32, i32, i32, i32, P, f64, P]
         L.orc_project_siddon.restype = None
+        L.orc_backproject_siddon.argtypes = [P, P, P, P, i32, i32, i32, i32, P, f64, P]
+        L.orc_backproject_siddon.restype = None
         L.orc_l1.argtypes = [P, P, i64, P]
         L.orc_l1.restype = f64
         L.orc_adam.argtypes = [P, P, P, P, i64, f64, f64, f64, f64, i64]
@@ -206,6 +208,18 @@ def backproject(proj, dims, lo, inv_h, kind, views, nu, nv, step, length_scale=1
     V = np.zeros((dims[2], dims[1], dims[0]), np.float64)
     lib().orc_backproject(_p(proj), _p(d), _p(l), _p(h), int(kind), nviews, int(nu), int(nv),
                           _p(views), float(step), float(length_scale), _p(V))
+    return V
+
+
+def backproject_siddon(proj, dims, lo, inv_h, kind, views, nu, nv, length_scale=1.0):
+    """Transpose of project_siddon: float64 volume [nz, ny, nx]."""
+    proj = _c(proj, np.float64)
+    views = _c(views, np.float32)
+    nviews = views.shape[0]
+    d, l, h = _grid_args(dims, lo, inv_h, np.float64)
+    V = np.zeros((dims[2], dims[1], dims[0]), np.float64)
+    lib().orc_backproject_siddon(_p(proj), _p(d), _p(l), _p(h), int(kind), nviews, int(nu), int(nv),
+                                 _p(views), float(length_scale), _p(V))
     return V
 
 

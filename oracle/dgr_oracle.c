@@ -536,12 +536,60 @@ void orc_backproject(const double *proj, const int32_t dims[3], const double glo
 /* with the voxel values, times ell (Siddon 1985).  The line is the same    */
 /* infinite line as in O4.  Crossing parameters of every cell plane are     */
 /* gathered, sorted, and each interval is attributed to the cell holding    */
-/* its midpoint.  An independent geometry check, not the GPU's operator.    */
+/* its midpoint.  It checks the geometry of the ray march and is the        */
+/* reference of the library's exact-path projector and its transpose.       */
 /* ------------------------------------------------------------------------ */
 static int cmp_dbl(const void *a, const void *b)
 {
     double x = *(const double *)a, y = *(const double *)b;
     return (x > y) - (x < y);
+}
+
+/* Segments of ray (c, d) inside the grid: cells[q] (flat index, or -1 when */
+/* the midpoint falls outside by rounding) and lengths len[q]; ts holds at  */
+/* least dims[0] + dims[1] + dims[2] + 6 doubles.  Returns the count.       */
+static int64_t siddon_segments(const double c[3], const double d[3], const int32_t dims[3],
+                               const double glo[3], const double inv_h[3], double *ts,
+                               int64_t *cells, double *len)
+{
+    double tmin = -INFINITY, tmax = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        double lo = glo[a], hi = glo[a] + (double)dims[a] / inv_h[a];
+        if (d[a] == 0.0) {
+            if (!(c[a] > lo && c[a] < hi)) return 0;
+            continue;
+        }
+        double t0 = (lo - c[a]) / d[a], t1 = (hi - c[a]) / d[a];
+        if (t0 > t1) { double tt = t0; t0 = t1; t1 = tt; }
+        if (t0 > tmin) tmin = t0;
+        if (t1 < tmax) tmax = t1;
+    }
+    if (!(tmin < tmax)) return 0;
+    int64_t m = 0, k = 0;
+    ts[m++] = tmin;
+    ts[m++] = tmax;
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0.0) continue;
+        for (int64_t p = 0; p <= dims[a]; ++p) {
+            double t = (glo[a] + (double)p / inv_h[a] - c[a]) / d[a];
+            if (t > tmin && t < tmax) ts[m++] = t;
+        }
+    }
+    qsort(ts, (size_t)m, sizeof(double), cmp_dbl);
+    for (int64_t q = 0; q + 1 < m; ++q) {
+        double l = ts[q + 1] - ts[q];
+        if (l <= 0.0) continue;
+        double tm = 0.5 * (ts[q] + ts[q + 1]);
+        int64_t idx[3], inside = 1;
+        for (int a = 0; a < 3; ++a) {
+            idx[a] = (int64_t)floor((c[a] + tm * d[a] - glo[a]) * inv_h[a]);
+            if (idx[a] < 0 || idx[a] >= dims[a]) inside = 0;
+        }
+        cells[k] = inside ? (idx[2] * dims[1] + idx[1]) * dims[0] + idx[0] : -1;
+        len[k] = l;
+        ++k;
+    }
+    return k;
 }
 
 void orc_project_siddon(const double *V, const int32_t dims[3], const double glo[3],
@@ -553,52 +601,45 @@ void orc_project_siddon(const double *V, const int32_t dims[3], const double glo
     int64_t cap = (int64_t)dims[0] + dims[1] + dims[2] + 6;
 #pragma omp parallel
     {
-        double *ts = malloc(sizeof(double) * (size_t)cap);
+        double *ts = malloc(sizeof(double) * (size_t)cap), *len = malloc(sizeof(double) * (size_t)cap);
+        int64_t *cells = malloc(sizeof(int64_t) * (size_t)cap);
 #pragma omp for schedule(dynamic, 64)
         for (int64_t r = 0; r < nrays; ++r) {
             int64_t j = r / ((int64_t)nu * nv), iv = (r / nu) % nv, iu = r % nu;
             double c[3], d[3];
             ray_of(&G, j, iu, iv, c, d);
-            /* parametric interval inside the grid box */
-            double tmin = -INFINITY, tmax = INFINITY;
-            int miss = 0;
-            for (int a = 0; a < 3; ++a) {
-                double lo = glo[a], hi = glo[a] + (double)dims[a] / inv_h[a];
-                if (d[a] == 0.0) {
-                    if (!(c[a] > lo && c[a] < hi)) miss = 1;
-                    continue;
-                }
-                double t0 = (lo - c[a]) / d[a], t1 = (hi - c[a]) / d[a];
-                if (t0 > t1) { double tt = t0; t0 = t1; t1 = tt; }
-                if (t0 > tmin) tmin = t0;
-                if (t1 < tmax) tmax = t1;
-            }
+            int64_t k = siddon_segments(c, d, dims, glo, inv_h, ts, cells, len);
             double acc = 0.0;
-            if (!miss && tmin < tmax) {
-                int64_t m = 0;
-                ts[m++] = tmin;
-                ts[m++] = tmax;
-                for (int a = 0; a < 3; ++a) {
-                    if (d[a] == 0.0) continue;
-                    for (int64_t p = 0; p <= dims[a]; ++p) {
-                        double t = (glo[a] + (double)p / inv_h[a] - c[a]) / d[a];
-                        if (t > tmin && t < tmax) ts[m++] = t;
-                    }
-                }
-                qsort(ts, (size_t)m, sizeof(double), cmp_dbl);
-                for (int64_t q = 0; q + 1 < m; ++q) {
-                    double len = ts[q + 1] - ts[q];
-                    if (len <= 0.0) continue;
-                    double tm = 0.5 * (ts[q] + ts[q + 1]);
-                    int64_t idx[3];
-                    for (int a = 0; a < 3; ++a) idx[a] = (int64_t)floor((c[a] + tm * d[a] - glo[a]) * inv_h[a]);
-                    acc += len * vox_or_zero(V, dims, idx[0], idx[1], idx[2]);
-                }
-            }
+            for (int64_t q = 0; q < k; ++q)
+                if (cells[q] >= 0) acc += len[q] * V[cells[q]];
             proj[r] = length_scale * acc;
         }
-        free(ts);
+        free(ts); free(len); free(cells);
     }
+}
+
+/* Transpose of orc_project_siddon: V[i] = ell * sum over rays r and their  */
+/* segments in cell i of len * proj[r].  Rays are taken one after another.  */
+void orc_backproject_siddon(const double *proj, const int32_t dims[3], const double glo[3],
+                            const double inv_h[3], int32_t kind, int32_t n_views, int32_t nu, int32_t nv,
+                            const float *views, double length_scale, double *V)
+{
+    orc_geom G = {kind, n_views, nu, nv, views, 1.0, length_scale};
+    int64_t nrays = (int64_t)n_views * nu * nv;
+    int64_t cap = (int64_t)dims[0] + dims[1] + dims[2] + 6;
+    int64_t nvox = (int64_t)dims[0] * dims[1] * dims[2];
+    double *ts = malloc(sizeof(double) * (size_t)cap), *len = malloc(sizeof(double) * (size_t)cap);
+    int64_t *cells = malloc(sizeof(int64_t) * (size_t)cap);
+    for (int64_t i = 0; i < nvox; ++i) V[i] = 0.0;
+    for (int64_t r = 0; r < nrays; ++r) {
+        int64_t j = r / ((int64_t)nu * nv), iv = (r / nu) % nv, iu = r % nu;
+        double c[3], d[3];
+        ray_of(&G, j, iu, iv, c, d);
+        int64_t k = siddon_segments(c, d, dims, glo, inv_h, ts, cells, len);
+        for (int64_t q = 0; q < k; ++q)
+            if (cells[q] >= 0) V[cells[q]] += length_scale * len[q] * proj[r];
+    }
+    free(ts); free(len); free(cells);
 }
 
 /* ------------------------------------------------------------------------ */

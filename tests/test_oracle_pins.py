@@ -293,8 +293,11 @@ def _rays(geom, j):
     if geom.kind == 0:
         d = np.broadcast_to(v[0:3], pix.shape)
         o = pix
-    else:
+    elif geom.kind == 1:
         o = np.broadcast_to(v[0:3], pix.shape)
+        d = pix - o
+    else:  # fan: the source of row iv sits at a + iv e_v
+        o = np.broadcast_to(v[0:3] + iv[:, None, None] * v[9:12], pix.shape)
         d = pix - o
     d = d / np.linalg.norm(d, axis=-1, keepdims=True)
     c = o - np.sum(o * d, -1, keepdims=True) * d
@@ -409,6 +412,35 @@ def test_siddon_converges_to_ball_chords():
             want[j] = (2 * np.sqrt(np.clip(R * R - b2, 0, None))).reshape(31, 31)
         errs.append(np.abs(P - want).mean() / want.mean())
     assert errs[1] < 0.02 and 1.6 < errs[0] / errs[1] < 2.6, errs  # first order in h
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+def test_siddon_transpose(kind):
+    """The exact-path transpose: adjoint identity with the forward, and one
+    ray's backprojection sums to its chord through the grid box (slab
+    clipping, computed independently)."""
+    dims, lo, inv_h = (13, 11, 9), (-0.8125, -0.6875, -0.5625), (8.0, 8.0, 8.0)
+    rng = np.random.default_rng(30 + kind)
+    if kind == 0:
+        geom = inputs.parallel_geometry(5, 15, 11, 0.11, 0.07)
+    elif kind == 1:
+        geom = inputs.cone_geometry(5, 15, 11, 0.15, 3.0, 4.5, 0.07, length_scale=2.0)
+    else:
+        geom = inputs.fan_geometry(5, 15, 11, 0.15, 0.125, 3.0, 4.5, 0.07, arc=2.0, length_scale=2.0)
+    ell = geom.length_scale
+    x = rng.normal(size=(9, 11, 13))
+    Ax = oracle.project_siddon(x, dims, lo, inv_h, kind, geom.views, 15, 11, ell)
+    y = rng.normal(size=Ax.shape)
+    ATy = oracle.backproject_siddon(y, dims, lo, inv_h, kind, geom.views, 15, 11, ell)
+    assert abs(np.sum(Ax * y) - np.sum(x * ATy)) <= 1e-12 * np.sqrt(np.sum(Ax ** 2) * np.sum(y ** 2))
+    one = np.zeros_like(y)
+    one[2, 5, 7] = 1.0
+    B = oracle.backproject_siddon(one, dims, lo, inv_h, kind, geom.views, 15, 11, ell)
+    c, d = _rays(geom, 2)
+    hi = np.array(lo) + np.array(dims) / np.array(inv_h)
+    chord = _slab_chord(c[5 * 15 + 7], d[5 * 15 + 7], np.array(lo), hi)
+    assert chord > 0 and abs(B.sum() - ell * chord) < 1e-12 * ell * chord
+    assert np.count_nonzero(B) > 5
 
 
 def test_raymarch_and_siddon_agree_on_smooth_volume():
