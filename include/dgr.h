@@ -169,6 +169,28 @@ dgr_status dgr_project_l1(const float *volume, const dgr_grid *grid, const dgr_g
 dgr_status dgr_backproject(const float *proj, const dgr_grid *grid, const dgr_geometry *geom,
                            float *volume, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- exact-path projection (Siddon) and its transpose ------------------- */
+
+/* proj[r] = length_scale * sum over voxels of |ray_r inside voxel| * volume,
+ * the voxels being constant-valued cells [lo + i h, lo + (i+1) h] (an
+ * alternative to the trilinear march for the abstract projector T of
+ * sec. 4.3; Siddon's exact radiological path).  The rays are the same lines
+ * as in dgr_project (any geometry kind; geom->step is not used).  Each ray
+ * is walked in binary64 and each segment between consecutive cell-plane
+ * crossings goes to the cell holding its midpoint.  proj [n_views][nv][nu]
+ * is overwritten.  No workspace. */
+dgr_status dgr_project_siddon(const float *volume, const dgr_grid *grid, const dgr_geometry *geom,
+                              float *proj, void *stream);
+
+/* volume = transpose of dgr_project_siddon applied to proj, summed in a
+ * binary64 workspace with hardware binary64 atomics (the order of the adds
+ * varies, at the 1e-16 level) and rounded to binary32.  ws >=
+ * dgr_backproject_siddon_workspace(grid) bytes (8 per voxel), 256-byte
+ * aligned. */
+size_t dgr_backproject_siddon_workspace(const dgr_grid *grid);
+dgr_status dgr_backproject_siddon(const float *proj, const dgr_grid *grid, const dgr_geometry *geom,
+                                  float *volume, void *ws, size_t ws_bytes, void *stream);
+
 /* ---- optimiser (sec. 5.1 Implementation Details: Adam) ------------------ */
 
 /* One Adam step in place over n entries, projected onto param >= lower:

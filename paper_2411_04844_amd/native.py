@@ -63,6 +63,9 @@ _SIGS = {
     "dgr_project": ("st", ["p", "grid", "geom", "p", "p", "sz", "p"]),
     "dgr_project_l1": ("st", ["p", "grid", "geom", "p", "p", "p", "p", "sz", "p"]),
     "dgr_backproject": ("st", ["p", "grid", "geom", "p", "p", "sz", "p"]),
+    "dgr_project_siddon": ("st", ["p", "grid", "geom", "p", "p"]),
+    "dgr_backproject_siddon_workspace": (ctypes.c_size_t, ["grid"]),
+    "dgr_backproject_siddon": ("st", ["p", "grid", "geom", "p", "p", "sz", "p"]),
     "dgr_adam": ("st", ["p", "p", "p", "p", "i64", "f32", "f32", "f32", "f32", "i64", "f32", "p"]),
     "dgr_bbox": ("st", ["p", "p", "p", "i64", "grid", "trunc", "p", "p"]),
     "dgr_bin": ("st", ["p", "p", "p", "i64", "grid", "trunc", "p", "p", "p", "sz", "p"]),
@@ -295,6 +298,33 @@ def dgr_backproject(proj, grid: GridSpec, geom: Geometry, views_dev, out=None,
     p, sz = ws.ptr_size(lib().dgr_project_workspace(ctypes.byref(g), ctypes.byref(G)))
     _check("dgr_backproject", lib().dgr_backproject(_ptr(proj), ctypes.byref(g), ctypes.byref(G),
                                                     _ptr(out), p, sz, _stream()))
+    return out
+
+
+def dgr_project_siddon(volume, grid: GridSpec, geom: Geometry, views_dev, out=None):
+    """Exact-path (Siddon) projection, float32 [n_views, nv, nu]."""
+    _need(volume, torch.float32, grid.shape, "volume")
+    if out is None:
+        out = torch.empty((geom.n_views, geom.nv, geom.nu), dtype=torch.float32, device=volume.device)
+    _need(out, torch.float32, (geom.n_views, geom.nv, geom.nu), "out")
+    g, G = c_grid(grid), c_geom(geom, views_dev)
+    _check("dgr_project_siddon", lib().dgr_project_siddon(_ptr(volume), ctypes.byref(g), ctypes.byref(G),
+                                                          _ptr(out), _stream()))
+    return out
+
+
+def dgr_backproject_siddon(proj, grid: GridSpec, geom: Geometry, views_dev, out=None,
+                           ws: Workspace | None = None):
+    """Transpose of dgr_project_siddon, float32 volume [nz, ny, nx]."""
+    _need(proj, torch.float32, (geom.n_views, geom.nv, geom.nu), "proj")
+    if out is None:
+        out = torch.empty(grid.shape, dtype=torch.float32, device=proj.device)
+    _need(out, torch.float32, grid.shape, "out")
+    ws = ws or Workspace(proj.device)
+    g, G = c_grid(grid), c_geom(geom, views_dev)
+    p, sz = ws.ptr_size(lib().dgr_backproject_siddon_workspace(ctypes.byref(g)))
+    _check("dgr_backproject_siddon", lib().dgr_backproject_siddon(_ptr(proj), ctypes.byref(g), ctypes.byref(G),
+                                                                  _ptr(out), p, sz, _stream()))
     return out
 
 
