@@ -16,8 +16,13 @@
  *   buffer, including the workspace `ws`; the library keeps no device state
  *   between calls and never allocates device memory.
  * - Streams: `stream` is a hipStream_t (NULL = the default stream).  Every call
- *   only enqueues work and returns; the only call that waits for the device is
- *   dgr_voxelize_plan (it returns a count to the host) and dgr_check.
+ *   only enqueues work and returns, except those that hand results to the
+ *   host and therefore synchronise `stream`: dgr_voxelize_plan, dgr_densify,
+ *   dgr_fd_l1_f64 and dgr_check.
+ * - Workspaces are 256-byte aligned.  The workspace of the voxelization calls
+ *   (dgr_voxelize_plan, dgr_voxelize, dgr_voxelize_f64, dgr_bin) carries a
+ *   pair-overflow flag from one call to the next: zero-fill it once before its
+ *   first use.  Other workspaces need no initial contents.
  * - Outputs are overwritten, never accumulated into.
  * - Errors: argument checks happen on the host before anything is enqueued;
  *   on failure nothing is launched and a status other than DGR_OK is
