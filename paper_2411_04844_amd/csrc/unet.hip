@@ -26,11 +26,11 @@
 // the decoder reads, so concatenation costs nothing.
 //
 // Kernels:
-//   conv3_mfma   implicit GEMM (M = voxels, N = output channels,
-//                K = 27 x input channels) on v_mfma_f32_16x16x32_bf16; A and B
-//                fragments are loaded straight from memory (8 contiguous
-//                channels per lane).  The data gradient is the same kernel
-//                with transposed, tap-reversed weights.
+//   conv3_tile   implicit GEMM (M = voxels, N = output channels,
+//                K = 27 x input channels) on v_mfma_f32_16x16x32_bf16 over
+//                16 x 4 x 4 voxel tiles whose halo is staged in LDS once per
+//                32-channel block and read by all 27 taps.  The data gradient
+//                is the same kernel with transposed, tap-reversed weights.
 //   conv3_wgrad  dW[t] = dY^T shift_t(X): K = voxels, so 128-voxel tiles of
 //                both operands are transposed through LDS, three taps (the
 //                three x shifts) per work-group sharing the dY tile; split
@@ -73,78 +73,98 @@ __device__ __forceinline__ void vox_coords(const Vol &d, int64_t v, int *x, int 
 }
 
 // ---- implicit-GEMM 3x3x3 convolution on the matrix cores ---------------------
-// Work-group: 256 voxels (4 waves x 64) x 16*NT output channels.  Each wave
-// holds 4 x NT accumulator tiles of 16x16.  Lane l of a wave owns rows
-// (voxels) l%16 + 16 m of A and columns l%16 + 16 n of B; its 8-element
-// K slice is 8 (l/16) .. 8 (l/16) + 7 within each 32-channel K block.
+// M = voxels, N = output channels, K = 27 taps x input channels, on
+// v_mfma_f32_16x16x32_bf16: lane l of a wave holds rows (voxels) l%16 of A
+// and columns l%16 of B with the 8-element K slice 8 (l/16) .. 8 (l/16) + 7
+// of each 32-channel block, and D[4 (l/16) + i][l%16] of each 16x16 tile.
 // x: bf16 [V][xs] (channels 0..cin-1 used); w: bf16 [27][cout][cin];
 // y: bf16 [V][ys] (channels 0..cout-1 written).  cin % 32 == 0, xs % 8 == 0,
 // ys % 8 == 0, pointers 16-byte aligned.
+// Work-group: a 16 x 4 x 4 voxel tile (x fastest) x 16*NT output channels.
+// For each 32-channel K block the tile's 18 x 6 x 6 halo of x is staged in
+// LDS once ([hz][hy][hx], 32 channels per voxel at a pitch of 40 u16 so the
+// 16-byte reads of 16 neighbouring voxels fall in distinct banks; zeros
+// outside the volume), and all 27 taps read their A fragments there: wave w
+// owns the tile's z-slice w, whose 4 rows of 16 voxels are its 4 M tiles;
+// lane (r, g) reads voxel (r + dx, m + dy, w + dz) of the halo.  B fragments
+// (weights) come from memory (small, cached).
+constexpr int kTX = 16, kTY = 4, kTZ = 4;
+constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2;
+constexpr int kHalo = kHX * kHY * kHZ;  // 648 voxels
+constexpr int kHPitch = 40;             // u16 per halo voxel (32 used)
+
 template <int NT>
-__global__ __launch_bounds__(256) void conv3_mfma(const u16 *__restrict__ x, int xs, Vol d, int cin,
+__global__ __launch_bounds__(256) void conv3_tile(const u16 *__restrict__ x, int xs, Vol d, int cin,
                                                   const u16 *__restrict__ w,
                                                   const float *__restrict__ bias, int cout, int relu,
                                                   u16 *__restrict__ y, int ys) {
+    __shared__ __attribute__((aligned(16))) u16 halo[kHalo * kHPitch];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = lane & 15, g = lane >> 4;
-    const int64_t vbase = ((int64_t)blockIdx.x * 4 + wave) * 64;
+    const int ntx = (d.nx + kTX - 1) / kTX, nty = (d.ny + kTY - 1) / kTY;
+    int tile = blockIdx.x;
+    const int tx = tile % ntx;
+    tile /= ntx;
+    const int ty = tile % nty, tz = tile / nty;
+    const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * kTZ;
     const int co0 = blockIdx.y * (16 * NT);
-    int vx[4], vy[4], vz[4];
-    bool vin[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        const int64_t v = vbase + m * 16 + r;
-        vin[m] = v < d.V;
-        vox_coords(d, vin[m] ? v : 0, &vx[m], &vy[m], &vz[m]);
-    }
     f32x4 acc[4][NT];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
         for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    const bf16x8 zero = __builtin_bit_cast(bf16x8, u32x4{0u, 0u, 0u, 0u});
-    for (int t = 0; t < 27; ++t) {
-        const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-        const u16 *xp[4];
-        bool ok[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int xx = vx[m] + dx, yy = vy[m] + dy, zz = vz[m] + dz;
-            ok[m] = vin[m] && xx >= 0 && yy >= 0 && zz >= 0 && xx < d.nx && yy < d.ny && zz < d.nz;
-            const int64_t vn = ok[m] ? ((int64_t)zz * d.ny + yy) * d.nx + xx : 0;
-            xp[m] = x + vn * xs + 8 * g;
+    for (int kb = 0; kb < cin; kb += 32) {
+        for (int q = threadIdx.x; q < kHalo * 4; q += 256) {
+            const int hv = q >> 2, c8 = (q & 3) * 8;
+            const int hx = hv % kHX, hr = hv / kHX;
+            const int hy = hr % kHY, hz = hr / kHY;
+            const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+            u32x4 val = u32x4{0u, 0u, 0u, 0u};
+            if (gx >= 0 && gy >= 0 && gz >= 0 && gx < d.nx && gy < d.ny && gz < d.nz)
+                val = *reinterpret_cast<const u32x4 *>(x + (((int64_t)gz * d.ny + gy) * d.nx + gx) * xs + kb + c8);
+            *reinterpret_cast<u32x4 *>(halo + hv * kHPitch + c8) = val;
         }
-        const u16 *wp = w + ((int64_t)t * cout + co0 + r) * cin + 8 * g;
-        for (int kb = 0; kb < cin; kb += 32) {
+        __syncthreads();
+#pragma unroll 3
+        for (int t = 0; t < 27; ++t) {
+            const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
             bf16x8 a[4], b[NT];
 #pragma unroll
-            for (int m = 0; m < 4; ++m) a[m] = ok[m] ? *reinterpret_cast<const bf16x8 *>(xp[m] + kb) : zero;
+            for (int m = 0; m < 4; ++m) {
+                const int hv = ((wave + 1 + dz) * kHY + (m + 1 + dy)) * kHX + (r + 1 + dx);
+                a[m] = *reinterpret_cast<const bf16x8 *>(halo + hv * kHPitch + 8 * g);
+            }
+            const u16 *wp = w + ((int64_t)t * cout + co0 + r) * cin + kb + 8 * g;
 #pragma unroll
-            for (int n = 0; n < NT; ++n) b[n] = *reinterpret_cast<const bf16x8 *>(wp + (int64_t)n * 16 * cin + kb);
+            for (int n = 0; n < NT; ++n) b[n] = *reinterpret_cast<const bf16x8 *>(wp + (int64_t)n * 16 * cin);
 #pragma unroll
             for (int m = 0; m < 4; ++m)
 #pragma unroll
                 for (int n = 0; n < NT; ++n)
                     acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b[n], acc[m][n], 0, 0, 0);
         }
+        __syncthreads();
     }
-    // lane holds D[4 g + i][r] of every tile: voxel vbase + 16 m + 4 g + i,
-    // channel co0 + 16 n + r
+    // lane holds D[4 g + i][r] of tile (m, n): voxel (x0 + 4 g + i, y0 + m,
+    // z0 + wave), channel co0 + 16 n + r
+    const int gz = z0 + wave;
 #pragma unroll
     for (int n = 0; n < NT; ++n) {
         const int co = co0 + n * 16 + r;
         const float bb = bias ? bias[co] : 0.0f;
 #pragma unroll
-        for (int m = 0; m < 4; ++m)
+        for (int m = 0; m < 4; ++m) {
+            const int gy = y0 + m;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int64_t v = vbase + m * 16 + 4 * g + i;
-                if (v < d.V) {
+                const int gx = x0 + 4 * g + i;
+                if (gx < d.nx && gy < d.ny && gz < d.nz) {
                     float val = acc[m][n][i] + bb;
                     if (relu) val = fmaxf(val, 0.0f);
-                    y[v * ys + co] = f2bf(val);
+                    y[(((int64_t)gz * d.ny + gy) * d.nx + gx) * ys + co] = f2bf(val);
                 }
             }
+        }
     }
 }
 
@@ -731,11 +751,12 @@ dgr_status check_unet(const int32_t dims[3], int B, Net *n, void *ws, size_t ws_
 
 dgr_status launch_conv(const u16 *x, int xs, const Vol &d, int cin, const u16 *w, const float *bias,
                        int cout, int relu, u16 *y, int ys, hipStream_t st) {
-    const dim3 grid((unsigned)((d.V + 255) / 256), (unsigned)(cout % 64 == 0 ? cout / 64 : cout / 32));
+    const int64_t tiles = (int64_t)((d.nx + kTX - 1) / kTX) * ((d.ny + kTY - 1) / kTY) * ((d.nz + kTZ - 1) / kTZ);
+    const dim3 grid((unsigned)tiles, (unsigned)(cout % 64 == 0 ? cout / 64 : cout / 32));
     if (cout % 64 == 0)
-        conv3_mfma<4><<<grid, dim3(256), 0, st>>>(x, xs, d, cin, w, bias, cout, relu, y, ys);
+        conv3_tile<4><<<grid, dim3(256), 0, st>>>(x, xs, d, cin, w, bias, cout, relu, y, ys);
     else
-        conv3_mfma<2><<<grid, dim3(256), 0, st>>>(x, xs, d, cin, w, bias, cout, relu, y, ys);
+        conv3_tile<2><<<grid, dim3(256), 0, st>>>(x, xs, d, cin, w, bias, cout, relu, y, ys);
     DGR_LAUNCH_CHECK();
     return DGR_OK;
 }
