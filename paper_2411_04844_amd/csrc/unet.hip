@@ -31,11 +31,10 @@
 //                16 x 4 x 4 voxel tiles whose halo is staged in LDS once per
 //                32-channel block and read by all 27 taps.  The data gradient
 //                is the same kernel with transposed, tap-reversed weights.
-//   conv3_wgrad  dW[t] = dY^T shift_t(X): K = voxels, so 128-voxel tiles of
-//                both operands are transposed through LDS, three taps (the
-//                three x shifts) per work-group sharing the dY tile; split
-//                over voxel chunks into binary32 partials summed in a fixed
-//                order.
+//   conv3_wgrad  dW[t] = dY^T shift_t(X): K = voxels; per 16 x 4 x 4 voxel
+//                tile dY and the x-shifted X halo are transposed into LDS and
+//                9 taps share each dY fragment; split over chunks of tiles
+//                into binary32 partials summed in a fixed order.
 //   conv1_*      the 1-channel first layer on the VALU (K = 27).
 //   pooling, upsampling (with the ReLU masks of the backward fused in), the
 //   1x1 head and the loss are elementwise VALU kernels.
@@ -169,22 +168,21 @@ __global__ __launch_bounds__(256) void conv3_tile(const u16 *__restrict__ x, int
 }
 
 // ---- weight gradient ------------------------------------------------------------
-// Grid: x = 9 (dz, dy) tap rows x (cout / 32) x (cin / 32) tiles, y = voxel
-// chunks.  Each work-group accumulates dW[t][co0 .. co0+31][ci0 .. ci0+31]
-// for the three taps t = (dz, dy, dx = -1, 0, 1) of its row over its chunk:
-// per 128-voxel step it stages dY[v][co] once and X[v + (dx, dy, dz)][ci]
-// for the three dx, all transposed in LDS ([channel][voxel], so the K =
-// voxel slice of a lane is contiguous and 16-byte aligned); wave w owns the
-// 16x16 sub-tile (co0 + 16 (w / 2), ci0 + 16 (w % 2)) of each tap and issues
-// 12 MFMAs per step, reading each dY fragment once for the three taps.
-// Loader threads 0..127 stage dY, 128..255 stage X: each takes 8 channels of
-// 4 consecutive voxels and writes, per channel, the 4 voxels as one 64-bit
-// LDS word (for X, once per dx; the three loads of neighbouring voxels
-// share cache lines).
-constexpr int kWgStep = 128;
-constexpr int kWgPitch = kWgStep + 8;  // u16 per LDS row (272 bytes, 16-byte aligned)
+// dW[t][co][ci] = sum_v dY[v][co] X[v + t][ci]: K = voxels.  Grid: x = 3 x
+// shifts (dx) x (cout / 32) x (cin / 32) channel blocks, y = chunks of the
+// 16 x 4 x 4 voxel tiles (the tiles of conv3_tile).  Per tile a work-group
+// stages, transposed in LDS, dY of the tile's 256 voxels ([co][v], v = x +
+// 16 (y + 4 z)) and X over the tile's (dy, dz) halo shifted by its dx
+// ([ci][hz][hy][x], 6 x 6 rows of 16), so that the 8-voxel K slice of a lane
+// is contiguous and 16-byte aligned in both; then wave w, owning the 16x16
+// sub-tile (co0 + 16 (w / 2), ci0 + 16 (w % 2)), runs the 9 (dy, dz) taps x 8
+// K blocks of 32 voxels = 72 MFMAs per tile, each dY fragment read once for
+// the 9 taps.  Loaders take 8 channels of 4 consecutive voxels (along x) and
+// write, per channel, the 4 voxels as one 64-bit LDS word.
+constexpr int kWgPitchA = 256 + 8;      // u16 per dY row (one channel, 256 voxels)
+constexpr int kWgPitchB = 6 * 6 * 16 + 8;  // u16 per X row (one channel, 6 x 6 x 16 voxels)
 
-__device__ __forceinline__ void store_transposed(u16 *dst, int c8, int vg, const u32x4 (&q)[4]) {
+__device__ __forceinline__ void store_transposed(u16 *dst, int pitch, int c8, int vg, const u32x4 (&q)[4]) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
         const int sh = (j & 1) * 16;
@@ -193,88 +191,86 @@ __device__ __forceinline__ void store_transposed(u16 *dst, int c8, int vg, const
             ((unsigned long long)((q[1][j >> 1] >> sh) & 0xffffu) << 16) |
             ((unsigned long long)((q[2][j >> 1] >> sh) & 0xffffu) << 32) |
             ((unsigned long long)((q[3][j >> 1] >> sh) & 0xffffu) << 48);
-        *reinterpret_cast<unsigned long long *>(dst + (c8 + j) * kWgPitch + vg) = w;
+        *reinterpret_cast<unsigned long long *>(dst + (c8 + j) * pitch + vg) = w;
     }
+}
+
+__device__ __forceinline__ u32x4 load8(const u16 *p, const Vol &d, int gx, int gy, int gz, int s) {
+    if (gx < 0 || gy < 0 || gz < 0 || gx >= d.nx || gy >= d.ny || gz >= d.nz) return u32x4{0u, 0u, 0u, 0u};
+    return *reinterpret_cast<const u32x4 *>(p + (((int64_t)gz * d.ny + gy) * d.nx + gx) * s);
 }
 
 __global__ __launch_bounds__(256) void conv3_wgrad(const u16 *__restrict__ x, int xs, Vol d, int cin,
                                                    const u16 *__restrict__ dy, int dys, int cout,
-                                                   int64_t chunk, float *__restrict__ part) {
-    __shared__ __attribute__((aligned(16))) u16 At[32 * kWgPitch];      // [co][v]
-    __shared__ __attribute__((aligned(16))) u16 Bt[3][32 * kWgPitch];   // [dx][ci][v]
+                                                   float *__restrict__ part) {
+    __shared__ __attribute__((aligned(16))) u16 At[32 * kWgPitchA];  // [co][v]
+    __shared__ __attribute__((aligned(16))) u16 Bt[32 * kWgPitchB];  // [ci][hz][hy][x]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, g = lane >> 4;
     const int n_ci = cin / 32, n_co = cout / 32;
-    int tile = blockIdx.x;
-    const int ib = tile % n_ci;
-    tile /= n_ci;
-    const int cb = tile % n_co;
-    const int trow = tile / n_co;  // (dz + 1) * 3 + (dy + 1)
-    const int dz = trow / 3 - 1, dyy = trow % 3 - 1;
-    const int64_t v_begin = (int64_t)blockIdx.y * chunk;
-    const int64_t v_end = min(d.V, v_begin + chunk);
+    int blk = blockIdx.x;
+    const int ib = blk % n_ci;
+    blk /= n_ci;
+    const int cb = blk % n_co;
+    const int dx = blk / n_co - 1;
+    const int ntx = (d.nx + kTX - 1) / kTX, nty = (d.ny + kTY - 1) / kTY, ntz = (d.nz + kTZ - 1) / kTZ;
+    const int64_t ntiles = (int64_t)ntx * nty * ntz;
+    const int64_t t_begin = ntiles * blockIdx.y / gridDim.y, t_end = ntiles * (blockIdx.y + 1) / gridDim.y;
     const int msub = (wave >> 1) * 16, nsub = (wave & 1) * 16;
-    f32x4 acc[3];
+    f32x4 acc[9];
 #pragma unroll
-    for (int s = 0; s < 3; ++s) acc[s] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    const bool is_x = tid >= 128;
-    const int lt = tid & 127;
-    const int vg = (lt >> 2) * 4, c8 = (lt & 3) * 8;  // voxels vg..vg+3 of the step, channels c8..c8+7
-    for (int64_t v0 = v_begin; v0 < v_end; v0 += kWgStep) {
-        if (!is_x) {
+    for (int k = 0; k < 9; ++k) acc[k] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const int c8 = (tid & 3) * 8;  // 8 channels of every loader task
+    for (int64_t tile = t_begin; tile < t_end; ++tile) {
+        const int tx = (int)(tile % ntx), ty = (int)((tile / ntx) % nty), tz = (int)(tile / ((int64_t)ntx * nty));
+        const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * kTZ;
+        {   // dY: 64 groups of 4 voxels x 4 channel octets, one task per thread
+            const int vg = (tid >> 2) * 4;  // tile voxels vg .. vg + 3 (same row)
+            const int lx = vg & 15, ly = (vg >> 4) & 3, lz = vg >> 6;
             u32x4 q[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int64_t v = v0 + vg + i;
-                q[i] = v < v_end ? *reinterpret_cast<const u32x4 *>(dy + v * dys + cb * 32 + c8)
-                                 : u32x4{0u, 0u, 0u, 0u};
-            }
-            store_transposed(At, c8, vg, q);
-        } else {
-            u32x4 q[3][4];
+            for (int i = 0; i < 4; ++i) q[i] = load8(dy + cb * 32 + c8, d, x0 + lx + i, y0 + ly, z0 + lz, dys);
+            store_transposed(At, kWgPitchA, c8, vg, q);
+        }
+        // X rows (hz, hy) of the halo, shifted by dx: 144 groups x 4 octets
+        for (int task = tid; task < 144 * 4; task += 256) {
+            const int vg = (task >> 2) * 4;  // halo voxels vg .. vg + 3 (same row of 16)
+            const int hx = vg & 15, hr = vg >> 4, hy = hr % 6, hz = hr / 6;
+            const int oc8 = (task & 3) * 8;
+            u32x4 q[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int64_t v = v0 + vg + i;
-#pragma unroll
-                for (int s = 0; s < 3; ++s) q[s][i] = u32x4{0u, 0u, 0u, 0u};
-                if (v < v_end) {
-                    int px, py, pz;
-                    vox_coords(d, v, &px, &py, &pz);
-                    const int yy = py + dyy, zz = pz + dz;
-                    if (yy >= 0 && zz >= 0 && yy < d.ny && zz < d.nz) {
-                        const u16 *row = x + (((int64_t)zz * d.ny + yy) * d.nx) * xs + ib * 32 + c8;
-#pragma unroll
-                        for (int s = 0; s < 3; ++s) {
-                            const int xx = px + s - 1;
-                            if (xx >= 0 && xx < d.nx)
-                                q[s][i] = *reinterpret_cast<const u32x4 *>(row + (int64_t)xx * xs);
-                        }
-                    }
-                }
-            }
-#pragma unroll
-            for (int s = 0; s < 3; ++s) store_transposed(Bt[s], c8, vg, q[s]);
+            for (int i = 0; i < 4; ++i)
+                q[i] = load8(x + ib * 32 + oc8, d, x0 + hx + i + dx, y0 + hy - 1, z0 + hz - 1, xs);
+            store_transposed(Bt, kWgPitchB, oc8, vg, q);
         }
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < kWgStep; kk += 32) {
-            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(At + (msub + r) * kWgPitch + kk + 8 * g);
+        for (int kk = 0; kk < 8; ++kk) {
+            // K block kk: tile voxels 32 kk .. 32 kk + 31, i.e. rows (y, z) =
+            // (2 kk, 2 kk + 1) in units of 16; lane g takes row 2 kk + g / 2,
+            // x = 8 (g % 2) .. + 7
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(At + (msub + r) * kWgPitchA + kk * 32 + 8 * g);
+            const int row = 2 * kk + (g >> 1);  // = y + 4 z of the tile
+            const int ly = row & 3, lz = row >> 2, xo = 8 * (g & 1);
 #pragma unroll
-            for (int s = 0; s < 3; ++s) {
-                const bf16x8 b = *reinterpret_cast<const bf16x8 *>(Bt[s] + (nsub + r) * kWgPitch + kk + 8 * g);
-                acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[s], 0, 0, 0);
+            for (int k = 0; k < 9; ++k) {
+                const int dz = k / 3 - 1, dyy = k % 3 - 1;
+                const int hrow = (lz + 1 + dz) * 6 + (ly + 1 + dyy);
+                const bf16x8 b = *reinterpret_cast<const bf16x8 *>(Bt + (nsub + r) * kWgPitchB + hrow * 16 + xo);
+                acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[k], 0, 0, 0);
             }
         }
         __syncthreads();
     }
     // lane holds D[4 g + i][r] of each tap: co = cb*32 + msub + 4g + i, ci = ib*32 + nsub + r
 #pragma unroll
-    for (int s = 0; s < 3; ++s) {
-        float *out = part + ((int64_t)blockIdx.y * 27 + trow * 3 + s) * cout * cin;
+    for (int k = 0; k < 9; ++k) {
+        const int t = (k / 3) * 9 + (k % 3) * 3 + (dx + 1);  // (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)
+        float *out = part + ((int64_t)blockIdx.y * 27 + t) * cout * cin;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int co = cb * 32 + msub + 4 * g + i, ci = ib * 32 + nsub + r;
-            out[(int64_t)co * cin + ci] = acc[s][i];
+            out[(int64_t)co * cin + ci] = acc[k][i];
         }
     }
 }
@@ -688,7 +684,8 @@ constexpr int kLossBlocks = 1024;
 constexpr int kHeadBlocks = 1024;
 constexpr int kConv1Blocks = 2048;
 
-int wgrad_chunks(int64_t V) { return (int)std::max<int64_t>(1, std::min<int64_t>(64, V / 16384)); }
+// Voxel-tile chunks of the weight gradient: about 8 tiles of 256 voxels each.
+int wgrad_chunks(int64_t V) { return (int)std::max<int64_t>(1, std::min<int64_t>(256, V / 2048)); }
 
 UWs carve_unet(void *base, const Net &n) {
     UWs w;
@@ -765,9 +762,8 @@ dgr_status launch_conv(const u16 *x, int xs, const Vol &d, int cin, const u16 *w
 dgr_status launch_wgrad(const u16 *x, int xs, const Vol &d, int cin, const u16 *dy, int cout, float *part,
                         float *dW, float *db, hipStream_t st) {
     const int nc = wgrad_chunks(d.V);
-    const int64_t chunk = (d.V + nc - 1) / nc;
-    const dim3 grid((unsigned)(9 * (cout / 32) * (cin / 32)), (unsigned)nc);
-    conv3_wgrad<<<grid, dim3(256), 0, st>>>(x, xs, d, cin, dy, cout, cout, chunk, part);
+    const dim3 grid((unsigned)(3 * (cout / 32) * (cin / 32)), (unsigned)nc);
+    conv3_wgrad<<<grid, dim3(256), 0, st>>>(x, xs, d, cin, dy, cout, cout, part);
     DGR_LAUNCH_CHECK();
     const int64_t n = 27LL * cout * cin;
     sum_chunks<<<blocks_for(n), 256, 0, st>>>(part, nc, n, dW);
