@@ -337,28 +337,44 @@ __global__ __launch_bounds__(256) void conv1_fwd(const float *__restrict__ x, Vo
 }
 
 // part[block][t][c] = sum over the block's voxels of dy[v][c] x[v + t]; the
-// block's 256 threads are 8 voxel lanes x 32 channel lanes (B <= 32 per pass).
+// block walks its share of the 16 x 4 x 4 voxel tiles, stages each tile's
+// 18 x 6 x 6 halo of x in LDS, and its 256 threads are 8 voxel lanes x 32
+// channel lanes (B <= 32 per pass): per voxel one dy value times the 27
+// halo values at constant offsets.
 __global__ __launch_bounds__(256) void conv1_wgrad(const float *__restrict__ x, Vol d,
                                                    const u16 *__restrict__ dy, int dys, int B,
                                                    float *__restrict__ part) {
+    __shared__ float xh[kHalo];
     __shared__ float red[8][27][32];
     const int c = threadIdx.x & 31, j = threadIdx.x >> 5;
-    const int64_t per = (d.V + gridDim.x - 1) / gridDim.x;
-    const int64_t v0 = (int64_t)blockIdx.x * per, v1 = min(d.V, v0 + per);
+    const int ntx = (d.nx + kTX - 1) / kTX, nty = (d.ny + kTY - 1) / kTY, ntz = (d.nz + kTZ - 1) / kTZ;
+    const int64_t ntiles = (int64_t)ntx * nty * ntz;
+    const int64_t t_begin = ntiles * blockIdx.x / gridDim.x, t_end = ntiles * (blockIdx.x + 1) / gridDim.x;
     for (int cb = 0; cb < B; cb += 32) {
         float acc[27];
 #pragma unroll
         for (int t = 0; t < 27; ++t) acc[t] = 0.0f;
-        if (cb + c < B) {
-            for (int64_t v = v0 + j; v < v1; v += 8) {
-                const float g = bf2f(dy[v * dys + cb + c]);
-                int px, py, pz;
-                vox_coords(d, v, &px, &py, &pz);
+        for (int64_t tile = t_begin; tile < t_end; ++tile) {
+            const int tx = (int)(tile % ntx), ty = (int)((tile / ntx) % nty), tz = (int)(tile / ((int64_t)ntx * nty));
+            const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * kTZ;
+            __syncthreads();  // the previous tile's halo has been read
+            for (int q = threadIdx.x; q < kHalo; q += 256) {
+                const int hx = q % kHX, hr = q / kHX, hy = hr % kHY, hz = hr / kHY;
+                const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+                xh[q] = (gx >= 0 && gy >= 0 && gz >= 0 && gx < d.nx && gy < d.ny && gz < d.nz)
+                            ? x[((int64_t)gz * d.ny + gy) * d.nx + gx] : 0.0f;
+            }
+            __syncthreads();
+            if (cb + c < B) {
+                for (int v = j; v < kTX * kTY * kTZ; v += 8) {
+                    const int lx = v & 15, ly = (v >> 4) & 3, lz = v >> 6;
+                    const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+                    if (gx >= d.nx || gy >= d.ny || gz >= d.nz) continue;
+                    const float gv = bf2f(dy[(((int64_t)gz * d.ny + gy) * d.nx + gx) * dys + cb + c]);
+                    const float *hb = xh + (lz * kHY + ly) * kHX + lx;
 #pragma unroll
-                for (int t = 0; t < 27; ++t) {
-                    const int xx = px + t % 3 - 1, yy = py + (t / 3) % 3 - 1, zz = pz + t / 9 - 1;
-                    const bool in = xx >= 0 && yy >= 0 && zz >= 0 && xx < d.nx && yy < d.ny && zz < d.nz;
-                    acc[t] = fmaf(g, in ? x[((int64_t)zz * d.ny + yy) * d.nx + xx] : 0.0f, acc[t]);
+                    for (int t = 0; t < 27; ++t)
+                        acc[t] = fmaf(gv, hb[(t / 9) * (kHY * kHX) + ((t / 3) % 3) * kHX + t % 3], acc[t]);
                 }
             }
         }
