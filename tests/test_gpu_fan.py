@@ -205,3 +205,19 @@ def test_fan_sparse_view_and_limited_angle_loops_reconstruct():
         say("fan loop", name, "PSNR", round(psnr0, 2), "->", round(res["best_psnr"], 2))
     assert out["sparse60"][1] > max(30.0, out["sparse60"][0] + 3.0)
     assert out["limited90"][1] > out["limited90"][0] + 5.0
+
+
+def test_fan_single_row_equals_cone_central_row():
+    """One detector row: the fan-beam row's source is the cone source, so the
+    two projections (and backprojections) are the same numbers."""
+    say("fan single row")
+    fan = inputs.fan_geometry(7, 33, 1, 0.05, 1.0 / 24, 7.8125, 11.71875, 1.0 / 48)
+    cone = inputs.cone_geometry(7, 33, 1, 0.05, 7.8125, 11.71875, 1.0 / 48)
+    V = dev(_rand_volume(305))
+    a = native.dgr_project(V, GRID, fan, dev(fan.views)).cpu().numpy()
+    b = native.dgr_project(V, GRID, cone, dev(cone.views)).cpu().numpy()
+    assert np.count_nonzero(a) > 0.5 * a.size and np.array_equal(a, b)
+    g = dev(np.random.default_rng(306).normal(size=a.shape).astype(np.float32))
+    A = native.dgr_backproject(g, GRID, fan, dev(fan.views)).cpu().numpy()
+    B = native.dgr_backproject(g, GRID, cone, dev(cone.views)).cpu().numpy()
+    assert np.array_equal(A, B)

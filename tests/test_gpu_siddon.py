@@ -106,3 +106,19 @@ def test_siddon_full_size_sampled_views():
     err = rel_l2(P[sel], want)
     say("siddon full project rel_l2 (3 views)", err)
     assert err < TOL
+
+
+def test_siddon_full_size_transpose_sampled_views():
+    say("siddon full transpose")
+    grid = inputs.cube_grid(256)
+    geom = inputs.cone_workload(256, 360, 512, 0.8)
+    sel = [11, 190, 333]
+    g = np.zeros((geom.n_views, geom.nv, geom.nu), np.float32)
+    g[sel] = np.random.default_rng(402).normal(size=(len(sel), geom.nv, geom.nu))
+    views = torch.as_tensor(geom.views).cuda()
+    got = native.dgr_backproject_siddon(torch.as_tensor(g).cuda(), grid, geom, views).cpu().numpy()
+    want = oracle.backproject_siddon(g[sel].astype(np.float64), grid.dims, grid.lo, grid.inv_h, geom.kind,
+                                     geom.views[sel], geom.nu, geom.nv, geom.length_scale)
+    err = rel_l2(got, want)
+    say("siddon full transpose rel_l2 (3 views)", err)
+    assert err < TOL
