@@ -180,6 +180,20 @@ def test_fan_full_backproject_sampled_views_and_adjoint(full):
     assert rel < TOL
 
 
+def test_fan_full_fbp(full):
+    """Slice-by-slice fan-beam FBP of the 60-view workload's analytic
+    phantom data over the whole 256^3 volume."""
+    grid, geom, V, views = full
+    say("fan full fbp")
+    y = inputs.phantom_projections(inputs.ellipsoid_phantom(3002), geom)
+    got = native.dgr_fdk(y.cuda(), grid, geom, views).cpu().numpy()
+    want = oracle.fdk(y.numpy(), geom.views, geom.nu, geom.nv, 2 * math.pi, geom.length_scale, grid.dims,
+                      grid.lo, grid.inv_h, kind=2)
+    err = rel_l2(got, want)
+    say("fan full fbp rel_l2", err)
+    assert err < TOL
+
+
 # --------------------------------------------------------------------------
 # the reconstruction loop on fan-beam data (128^3, the two paper settings)
 # --------------------------------------------------------------------------
