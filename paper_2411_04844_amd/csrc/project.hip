@@ -17,8 +17,10 @@
 // position; no periodic re-anchoring is needed.
 // Forward: one thread per ray; the volume is read from a copy with a two-voxel
 // zero border, so the eight taps of any sample in the support need no test.
-// Backward: one work-group per 16^3-cell brick accumulates, over all views, the
-// samples whose trilinear cell lies in the brick into a 17^3 LDS tile (no
+// Backward: one work-group per 20 x 20 x 10-cell brick accumulates, over all
+// views, the samples whose trilinear cell lies in the brick into a 21 x 21 x 11
+// LDS tile (flat bricks: for nearly horizontal rays the detector footprint of a
+// brick, and with it the ray set-up, shrinks while the samples per ray grow; no
 // global atomics); the tiles are then summed per voxel.  The LDS sums are
 // 64-bit fixed point: the weights of the samples of one ray in one cell are
 // summed in registers, scaled by a power of two S chosen from max|proj| so that
@@ -35,9 +37,12 @@ namespace {
 
 constexpr int kPad = 2;
 constexpr int kXcd = 8;     // MI355X: work-groups are dealt round-robin to 8 XCDs
-constexpr int kB = 16;        // brick edge in cells (backward, <= 16: 4-bit local cells)
-constexpr int kBT = kB + 1;   // brick tile edge in voxels
-constexpr int kBT3 = kBT * kBT * kBT;
+// Backprojection bricks: kBX x kBY x kBZ cells (<= 32 each: 5-bit local
+// cells in the ray records), tiles one voxel larger per axis.
+constexpr int kBX = 20, kBY = 20, kBZ = 10;
+constexpr int kTBX = kBX + 1, kTBY = kBY + 1, kTBZ = kBZ + 1;
+constexpr int kBT3 = kTBX * kTBY * kTBZ;
+static_assert(kBX <= 32 && kBY <= 32 && kBZ <= 32, "local cells are 5-bit");
 
 struct PadDims {
     int px, py, pz;  // padded extents
@@ -66,9 +71,9 @@ struct Bricks {
 inline Bricks bricks_of(const dgr_grid *g) {
     // cells floor(u) range over [-1, dims-1]: dims + 1 values per axis
     Bricks b;
-    b.nx = (g->dims[0] + 1 + kB - 1) / kB;
-    b.ny = (g->dims[1] + 1 + kB - 1) / kB;
-    b.nz = (g->dims[2] + 1 + kB - 1) / kB;
+    b.nx = (g->dims[0] + 1 + kBX - 1) / kBX;
+    b.ny = (g->dims[1] + 1 + kBY - 1) / kBY;
+    b.nz = (g->dims[2] + 1 + kBZ - 1) / kBZ;
     return b;
 }
 
@@ -456,8 +461,8 @@ __global__ __launch_bounds__(256) void brick_rects(GeomDev G, DevGrid g, Bricks 
     const int64_t b = i - (int64_t)j * nb;
     const int bx = (int)(b % bk.nx), by = (int)((b / bk.nx) % bk.ny), bz = (int)(b / ((int64_t)bk.nx * bk.ny));
     // the brick's cells span voxel coordinates [c0, c0 + kB] (unpadded)
-    const double ulo[3] = {(double)(bx * kB - 1), (double)(by * kB - 1), (double)(bz * kB - 1)};
-    const double uhi[3] = {ulo[0] + kB, ulo[1] + kB, ulo[2] + kB};
+    const double ulo[3] = {(double)(bx * kBX - 1), (double)(by * kBY - 1), (double)(bz * kBZ - 1)};
+    const double uhi[3] = {ulo[0] + kBX, ulo[1] + kBY, ulo[2] + kBZ};
     int iu0, iu1, iv0, iv1;
     shadow_rect(G.kind, G.views + 12 * (int64_t)j, G.nu, G.nv, g, ulo, uhi, &iu0, &iu1, &iv0, &iv1);
     if (iu0 > iu1 || iv0 > iv1) { iu0 = 1; iu1 = 0; iv0 = 1; iv1 = 0; }
@@ -510,14 +515,15 @@ struct alignas(16) RayRec {  // 32 bytes
     unsigned ulo[3];  // low words of the brick-relative 32.32 position of sample k0
     float gr;         // weighted projection value, scaled to fixed point
     unsigned dlo[3];  // low words of the 32.32 advance per sample
-    unsigned meta;    // [0,12): high words of the position, 4 bits per axis, in [0, 16)
-                      // [12,24): high words of the advance, 4-bit two's complement
+    unsigned meta;    // [0,15): high words of the position, 5 bits per axis, in [0, 32)
+                      // [15,24): high words of the advance, 3-bit two's complement
                       // [24,32): number of samples - 1
 };
 
 __device__ __forceinline__ bool in_brick(long long x, long long y, long long z) {
-    constexpr unsigned long long lim = (unsigned long long)kB << 32;
-    return (unsigned long long)x < lim && (unsigned long long)y < lim && (unsigned long long)z < lim;
+    return (unsigned long long)x < ((unsigned long long)kBX << 32) &&
+           (unsigned long long)y < ((unsigned long long)kBY << 32) &&
+           (unsigned long long)z < ((unsigned long long)kBZ << 32);
 }
 
 __device__ __forceinline__ int wave_excl_scan(int v, int lane, int *total) {
@@ -533,15 +539,16 @@ __device__ __forceinline__ int wave_excl_scan(int v, int lane, int *total) {
 
 __device__ __forceinline__ void flush_cell(unsigned long long *tile, int lx, int ly, int lz,
                                            const float (&e)[8]) {
-    unsigned long long *q = tile + (lz * kBT + ly) * kBT + lx;
+    constexpr int sy = kTBX, sz = kTBX * kTBY;
+    unsigned long long *q = tile + (lz * kTBY + ly) * kTBX + lx;
     atomicAdd(q, (unsigned long long)(long long)(int)e[0]);
     atomicAdd(q + 1, (unsigned long long)(long long)(int)e[1]);
-    atomicAdd(q + kBT, (unsigned long long)(long long)(int)e[2]);
-    atomicAdd(q + kBT + 1, (unsigned long long)(long long)(int)e[3]);
-    atomicAdd(q + kBT * kBT, (unsigned long long)(long long)(int)e[4]);
-    atomicAdd(q + kBT * kBT + 1, (unsigned long long)(long long)(int)e[5]);
-    atomicAdd(q + kBT * kBT + kBT, (unsigned long long)(long long)(int)e[6]);
-    atomicAdd(q + kBT * kBT + kBT + 1, (unsigned long long)(long long)(int)e[7]);
+    atomicAdd(q + sy, (unsigned long long)(long long)(int)e[2]);
+    atomicAdd(q + sy + 1, (unsigned long long)(long long)(int)e[3]);
+    atomicAdd(q + sz, (unsigned long long)(long long)(int)e[4]);
+    atomicAdd(q + sz + 1, (unsigned long long)(long long)(int)e[5]);
+    atomicAdd(q + sz + sy, (unsigned long long)(long long)(int)e[6]);
+    atomicAdd(q + sz + sy + 1, (unsigned long long)(long long)(int)e[7]);
 }
 
 // Phase 2 over the queued segments: lane i of wave w takes segments
@@ -557,7 +564,8 @@ __device__ __forceinline__ void march_segments(unsigned long long *tile, const R
     // segments are queued together and neighbouring pixels one after the
     // other, so lanes side by side take segments about two rays apart and
     // rarely add into the same LDS word at once.  (Strides 2 ... 64 were
-    // timed; 8 gave the fewest LDS bank conflicts, 3 % faster than 32.)
+    // timed; on 16^3 bricks 8 gave the fewest LDS bank conflicts, 3 % faster
+    // than 32; on the flat bricks 4 ... 16 are within 0.5 %.)
     const int perm = ((t & 31) << 3) | (t >> 5);
     for (int base = 0; base < nsegs; base += 256) {
         const int s = base + perm;
@@ -566,12 +574,12 @@ __device__ __forceinline__ void march_segments(unsigned long long *tile, const R
         const RayRec rec = rays[e >> 3];
         const int seg = (int)(e & 7u);
         const unsigned m = rec.meta;
-        long long ux = (long long)(((unsigned long long)(m & 15u) << 32) | rec.ulo[0]);
-        long long uy = (long long)(((unsigned long long)((m >> 4) & 15u) << 32) | rec.ulo[1]);
-        long long uz = (long long)(((unsigned long long)((m >> 8) & 15u) << 32) | rec.ulo[2]);
-        const long long dx = (long long)(((unsigned long long)(long long)((int)(m << 16) >> 28) << 32) | rec.dlo[0]);
-        const long long dy = (long long)(((unsigned long long)(long long)((int)(m << 12) >> 28) << 32) | rec.dlo[1]);
-        const long long dz = (long long)(((unsigned long long)(long long)((int)(m << 8) >> 28) << 32) | rec.dlo[2]);
+        long long ux = (long long)(((unsigned long long)(m & 31u) << 32) | rec.ulo[0]);
+        long long uy = (long long)(((unsigned long long)((m >> 5) & 31u) << 32) | rec.ulo[1]);
+        long long uz = (long long)(((unsigned long long)((m >> 10) & 31u) << 32) | rec.ulo[2]);
+        const long long dx = (long long)(((unsigned long long)(long long)((int)(m << 14) >> 29) << 32) | rec.dlo[0]);
+        const long long dy = (long long)(((unsigned long long)(long long)((int)(m << 11) >> 29) << 32) | rec.dlo[1]);
+        const long long dz = (long long)(((unsigned long long)(long long)((int)(m << 8) >> 29) << 32) | rec.dlo[2]);
         const int n = (int)(m >> 24) + 1;
         const int k_off = seg * seg_len;
         const int cnt = min(seg_len, n - k_off);
@@ -615,7 +623,7 @@ __device__ __forceinline__ void march_segments(unsigned long long *tile, const R
 
 // seg_len: samples per segment, chosen on the host so that no ray in a brick
 // has more than kMaxSeg segments (and no more than 256 samples).
-// Three work-groups per CU (54 KB of LDS each, <= 168 VGPRs): the extra waves
+// Three work-groups per CU (53 KB of LDS each, <= 168 VGPRs): the extra waves
 // overlap one work-group's LDS adds with another's arithmetic.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void backproject_bricks(const float *__restrict__ proj, DevGrid g,
                                                           GeomDev G, Bricks bk,
@@ -632,7 +640,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     const int64_t nb = bk.count();
     const int bx = (int)(b % bk.nx), by = (int)((b / bk.nx) % bk.ny), bz = (int)(b / ((int64_t)bk.nx * bk.ny));
     // brick cells in padded coordinates: [c0, c0 + kB)
-    const int c0x = bx * kB - 1 + kPad, c0y = by * kB - 1 + kPad, c0z = bz * kB - 1 + kPad;
+    const int c0x = bx * kBX - 1 + kPad, c0y = by * kBY - 1 + kPad, c0z = bz * kBZ - 1 + kPad;
     const long long C0x = (long long)c0x << 32, C0y = (long long)c0y << 32, C0z = (long long)c0z << 32;
     // The candidate k-range is exact in binary64 for the brick grown by eps, a
     // bound on |fixed-point position - binary64 position|, so it holds every
@@ -640,7 +648,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     // run of k (each axis test is an interval of the exact integer positions);
     // the run's ends are found by testing the fixed-point cells.
     const double blo[3] = {c0x - (double)eps, c0y - (double)eps, c0z - (double)eps};
-    const double bhi[3] = {c0x + kB + (double)eps, c0y + kB + (double)eps, c0z + kB + (double)eps};
+    const double bhi[3] = {c0x + kBX + (double)eps, c0y + kBY + (double)eps, c0z + kBZ + (double)eps};
     const float gs = G.scale * fixed_scale(maxbits, G.scale, headroom);  // |proj * gs| < 2^(30 - headroom)
     for (int e = t; e < kBT3; e += 256) tile[e] = 0ull;
     if (t == 0) {
@@ -697,11 +705,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
                             rec.dlo[1] = (unsigned)r.DU[1];
                             rec.dlo[2] = (unsigned)r.DU[2];
                             rec.gr = gr;
-                            rec.meta = (unsigned)(ux >> 32) | ((unsigned)(uy >> 32) << 4) |
-                                       ((unsigned)(uz >> 32) << 8) |
-                                       (((unsigned)(r.DU[0] >> 32) & 15u) << 12) |
-                                       (((unsigned)(r.DU[1] >> 32) & 15u) << 16) |
-                                       (((unsigned)(r.DU[2] >> 32) & 15u) << 20) |
+                            rec.meta = (unsigned)(ux >> 32) | ((unsigned)(uy >> 32) << 5) |
+                                       ((unsigned)(uz >> 32) << 10) |
+                                       (((unsigned)(r.DU[0] >> 32) & 7u) << 15) |
+                                       (((unsigned)(r.DU[1] >> 32) & 7u) << 18) |
+                                       (((unsigned)(r.DU[2] >> 32) & 7u) << 21) |
                                        ((unsigned)(n - 1) << 24);
                         }
                     }
@@ -761,13 +769,14 @@ __global__ __launch_bounds__(256) void gather_bricks(const long long *__restrict
         const int vv[3] = {x, y, (int)z};
         int nb[3], bb[3][2], ll[3][2];
         for (int a = 0; a < 3; ++a) {
-            const int s = vv[a] + 1;  // local index in brick b is s - kB * b
-            bb[a][0] = s / kB;
-            ll[a][0] = s - kB * bb[a][0];
+            const int kb = a == 0 ? kBX : (a == 1 ? kBY : kBZ);
+            const int s = vv[a] + 1;  // local index in brick b is s - kb * b
+            bb[a][0] = s / kb;
+            ll[a][0] = s - kb * bb[a][0];
             nb[a] = 1;
             if (ll[a][0] == 0 && bb[a][0] > 0) {
                 bb[a][1] = bb[a][0] - 1;
-                ll[a][1] = kB;
+                ll[a][1] = kb;
                 nb[a] = 2;
             }
         }
@@ -776,7 +785,7 @@ __global__ __launch_bounds__(256) void gather_bricks(const long long *__restrict
             for (int iy = 0; iy < nb[1]; ++iy)
                 for (int ix = 0; ix < nb[0]; ++ix) {
                     const int64_t brick = ((int64_t)bb[2][iz] * bk.ny + bb[1][iy]) * bk.nx + bb[0][ix];
-                    acc += staging[brick * kBT3 + (ll[2][iz] * kBT + ll[1][iy]) * kBT + ll[0][ix]];
+                    acc += staging[brick * kBT3 + (ll[2][iz] * kTBY + ll[1][iy]) * kTBX + ll[0][ix]];
                 }
         V[i] = (float)((double)acc * inv_s);
     }
@@ -911,19 +920,20 @@ extern "C" dgr_status dgr_backproject(const float *proj, const dgr_grid *grid,
     dgr_status s = check_proj(grid, geom, ws, ws_bytes);
     if (s != DGR_OK) return s;
     DGR_CHECK(proj && volume, "null projection or volume pointer");
-    // Samples of one ray inside a 16-cell brick: along the axis where the unit
-    // direction is largest (>= 1/sqrt(3)) a sample advances by at least
-    // step * min(inv_h) / sqrt(3) cells.  The queue records hold at most 256
-    // samples per ray and advances below 8 cells per sample per axis.
+    // Samples of one ray inside a brick: its chord is at most the brick's
+    // diagonal, and samples are step * min(inv_h) cells apart or more.  The
+    // queue records hold at most 256 samples per ray and advances below 4
+    // cells per sample per axis (3-bit high words).
     double min_inv = 1e300, max_inv = 0.0;
     for (int a = 0; a < 3; ++a) {
         min_inv = std::min(min_inv, (double)grid->inv_h[a]);
         max_inv = std::max(max_inv, (double)grid->inv_h[a]);
     }
     const double step_min = (double)geom->step * min_inv;
-    const int max_n = (int)std::min(1e9, std::floor(kB * std::sqrt(3.0) * 1.0001 / step_min) + 2.0);
-    DGR_CHECK(max_n <= 256, "backprojection needs step >= 0.11 voxel (got %.4g)", step_min);
-    DGR_CHECK((double)geom->step * max_inv <= 7.9, "backprojection needs step <= 7.9 voxels");
+    const double chord = std::sqrt((double)kBX * kBX + (double)kBY * kBY + (double)kBZ * kBZ);
+    const int max_n = (int)std::min(1e9, std::floor(chord * 1.0001 / step_min) + 2.0);
+    DGR_CHECK(max_n <= 256, "backprojection needs step >= %.3g voxel (got %.4g)", chord / 254.0, step_min);
+    DGR_CHECK((double)geom->step * max_inv <= 3.9, "backprojection needs step <= 3.9 voxels");
     const int seg_len = std::max(8, (max_n + kMaxSeg - 1) / kMaxSeg);
     // samples of one ray inside one unit cell: at most sqrt(3) / step + 1
     const int per_cell = (int)std::floor(std::sqrt(3.0) * 1.0001 / step_min) + 1;
