@@ -24,7 +24,8 @@
 // global atomics); the tiles are then summed per voxel.  The LDS sums are
 // 64-bit fixed point: the weights of the samples of one ray in one cell are
 // summed in registers, scaled by a power of two S chosen from max|proj| so that
-// the sum fits in 32 bits, truncated to an integer and added with ds_add_u64.
+// the sum fits in 32 bits, converted to an integer (within one unit) and added
+// with ds_add_u64.
 // Integer addition makes the result independent of the order of the adds
 // between rays (the order within a ray is fixed).
 #include <algorithm>
@@ -538,17 +539,18 @@ __device__ __forceinline__ int wave_excl_scan(int v, int lane, int *total) {
 }
 
 __device__ __forceinline__ void flush_cell(unsigned long long *tile, int lx, int ly, int lz,
-                                           const float (&e)[8]) {
-    constexpr int sy = kTBX, sz = kTBX * kTBY;
-    unsigned long long *q = tile + (lz * kTBY + ly) * kTBX + lx;
-    atomicAdd(q, (unsigned long long)(long long)(int)e[0]);
-    atomicAdd(q + 1, (unsigned long long)(long long)(int)e[1]);
-    atomicAdd(q + sy, (unsigned long long)(long long)(int)e[2]);
-    atomicAdd(q + sy + 1, (unsigned long long)(long long)(int)e[3]);
-    atomicAdd(q + sz, (unsigned long long)(long long)(int)e[4]);
-    atomicAdd(q + sz + 1, (unsigned long long)(long long)(int)e[5]);
-    atomicAdd(q + sz + sy, (unsigned long long)(long long)(int)e[6]);
-    atomicAdd(q + sz + sy + 1, (unsigned long long)(long long)(int)e[7]);
+                                           const float (&e)[8], unsigned hi) {
+    constexpr unsigned sy = kTBX, sz = kTBX * kTBY;
+    unsigned long long *q = tile + (__umul24((unsigned)lz, sz) + __umul24((unsigned)ly, sy) + (unsigned)lx);
+    const unsigned long long h = (unsigned long long)hi << 32;
+    atomicAdd(q, h | (unsigned)(int)e[0]);
+    atomicAdd(q + 1, h | (unsigned)(int)e[1]);
+    atomicAdd(q + sy, h | (unsigned)(int)e[2]);
+    atomicAdd(q + sy + 1, h | (unsigned)(int)e[3]);
+    atomicAdd(q + sz, h | (unsigned)(int)e[4]);
+    atomicAdd(q + sz + 1, h | (unsigned)(int)e[5]);
+    atomicAdd(q + sz + sy, h | (unsigned)(int)e[6]);
+    atomicAdd(q + sz + sy + 1, h | (unsigned)(int)e[7]);
 }
 
 // Phase 2 over the queued segments: lane i of wave w takes segments
@@ -587,37 +589,50 @@ __device__ __forceinline__ void march_segments(unsigned long long *tile, const R
         uy += (long long)k_off * dy;
         uz += (long long)k_off * dz;
         const float gr = rec.gr;
+        // Fixed-point conversion: every corner value of a ray has the sign of
+        // gr, so the high word of its 64-bit integer is the sign of gr.  The
+        // accumulators start at 0.5 (positive: truncation rounds to nearest)
+        // or -1 (negative: the integer is -1 or less, never 0, which would
+        // need a high word of 0).
+        const float gr32 = gr * kInv32;  // exact: a power-of-two scale
+        const unsigned hi = gr < 0.0f ? 0xffffffffu : 0u;
+        const float a_init = gr < 0.0f ? -1.0f : 0.5f;
         int cx = (int)(ux >> 32), cy = (int)(uy >> 32), cz = (int)(uz >> 32);
-        float acc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        float acc[8] = {a_init, a_init, a_init, a_init, a_init, a_init, a_init, a_init};
         for (int i = 0; i < cnt; ++i) {
             const int lx = (int)(ux >> 32), ly = (int)(uy >> 32), lz = (int)(uz >> 32);
-            const float wx = (float)(unsigned)ux * kInv32;
-            const float wy = (float)(unsigned)uy * kInv32;
-            const float wz = (float)(unsigned)uz * kInv32;
+            // 2^32 times the trilinear weights of the upper corners
+            const float fx = (float)(unsigned)ux, fy = (float)(unsigned)uy, fz = (float)(unsigned)uz;
             ux += dx;
             uy += dy;
             uz += dz;
             if (lx != cx || ly != cy || lz != cz) {
-                flush_cell(tile, cx, cy, cz, acc);
+                flush_cell(tile, cx, cy, cz, acc, hi);
 #pragma unroll
-                for (int c = 0; c < 8; ++c) acc[c] = 0.0f;
+                for (int c = 0; c < 8; ++c) acc[c] = a_init;
                 cx = lx;
                 cy = ly;
                 cz = lz;
             }
-            const float z1 = gr * wz, z0 = gr - z1;
-            const float y01 = z0 * wy, y00 = z0 - y01, y11 = z1 * wy, y10 = z1 - y11;
-            const float a0 = y00 * wx, a1 = y01 * wx, a2 = y10 * wx, a3 = y11 * wx;
-            acc[0] += y00 - a0;
-            acc[1] += a0;
-            acc[2] += y01 - a1;
-            acc[3] += a1;
-            acc[4] += y10 - a2;
-            acc[5] += a2;
-            acc[6] += y11 - a3;
-            acc[7] += a3;
+            // Every corner value is a product of gr and non-negative factors,
+            // added with an explicit fma, so it has the sign of gr whatever
+            // the compiler contracts (a difference such as z1 - z1 * wy, fused
+            // with an unrounded product, could flip the sign of a rounding
+            // residue and break the high word above).
+            const float z1 = gr32 * fz, z0 = gr * fmaf(-fz, kInv32, 1.0f);
+            const float wy = fy * kInv32, oy = fmaf(-fy, kInv32, 1.0f);
+            const float y00 = z0 * oy, y01 = z0 * wy, y10 = z1 * oy, y11 = z1 * wy;
+            const float wx = fx * kInv32, ox = fmaf(-fx, kInv32, 1.0f);
+            acc[0] = fmaf(y00, ox, acc[0]);
+            acc[1] = fmaf(y00, wx, acc[1]);
+            acc[2] = fmaf(y01, ox, acc[2]);
+            acc[3] = fmaf(y01, wx, acc[3]);
+            acc[4] = fmaf(y10, ox, acc[4]);
+            acc[5] = fmaf(y10, wx, acc[5]);
+            acc[6] = fmaf(y11, ox, acc[6]);
+            acc[7] = fmaf(y11, wx, acc[7]);
         }
-        flush_cell(tile, cx, cy, cz, acc);
+        flush_cell(tile, cx, cy, cz, acc, hi);
     }
 }
 

@@ -168,8 +168,9 @@ def test_fan_full_backproject_sampled_views_and_adjoint(full):
     want = oracle.backproject(g[sel].astype(np.float64), grid.dims, grid.lo, grid.inv_h, geom.kind,
                               geom.views[sel], geom.nu, geom.nv, geom.step, geom.length_scale)
     err = rel_l2(got, want)
-    say("fan full backproject rel_l2 (3 views)", err)
-    assert err < TOL
+    worst = float(np.abs(got.astype(np.float64) - want).max() / np.abs(want).max())
+    say("fan full backproject rel_l2 (3 views)", err, "worst voxel / max", worst)
+    assert err < TOL and worst < 1e-5
     x = torch.as_tensor(rng.normal(size=grid.shape).astype(np.float32)).cuda()
     y = torch.as_tensor(rng.normal(size=(geom.n_views, geom.nv, geom.nu)).astype(np.float32)).cuda()
     Ax = native.dgr_project(x, grid, geom, views).double()

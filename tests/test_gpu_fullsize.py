@@ -79,8 +79,12 @@ def test_full_backproject_sampled_views_and_adjoint(full):
     want = oracle.backproject(g[sel].astype(np.float64), grid.dims, grid.lo, grid.inv_h, geom.kind,
                               geom.views[sel], geom.nu, geom.nv, geom.step, geom.length_scale)
     err = rel_l2(got, want)
-    say("full backproject rel_l2 (4 views)", err)
+    worst = float(np.abs(got.astype(np.float64) - want).max() / np.abs(want).max())
+    say("full backproject rel_l2 (4 views)", err, "worst voxel / max", worst)
     assert err < TOL
+    # no single voxel may be off either (a wrong high word of one fixed-point
+    # add shows as a few voxels off by 2^32 units, small in the L2 norm)
+    assert worst < 1e-5
     # adjoint identity over all 360 views, binary32 on both sides
     x = torch.as_tensor(rng.normal(size=grid.shape).astype(np.float32)).cuda()
     y = torch.as_tensor(rng.normal(size=(geom.n_views, geom.nv, geom.nu)).astype(np.float32)).cuda()
