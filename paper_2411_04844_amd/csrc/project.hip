@@ -538,10 +538,12 @@ __device__ __forceinline__ int wave_excl_scan(int v, int lane, int *total) {
     return incl - v;
 }
 
-__device__ __forceinline__ void flush_cell(unsigned long long *tile, int lx, int ly, int lz,
-                                           const float (&e)[8], unsigned hi) {
+// Adds the eight corner values e of the cell whose lower corner is tile entry
+// `cell` (x fastest); hi is the high word of all eight (the sign of e).
+__device__ __forceinline__ void flush_cell(unsigned long long *tile, unsigned cell, const float (&e)[8],
+                                           unsigned hi) {
     constexpr unsigned sy = kTBX, sz = kTBX * kTBY;
-    unsigned long long *q = tile + (__umul24((unsigned)lz, sz) + __umul24((unsigned)ly, sy) + (unsigned)lx);
+    unsigned long long *q = tile + cell;
     const unsigned long long h = (unsigned long long)hi << 32;
     atomicAdd(q, h | (unsigned)(int)e[0]);
     atomicAdd(q + 1, h | (unsigned)(int)e[1]);
@@ -551,6 +553,12 @@ __device__ __forceinline__ void flush_cell(unsigned long long *tile, int lx, int
     atomicAdd(q + sz + 1, h | (unsigned)(int)e[5]);
     atomicAdd(q + sz + sy, h | (unsigned)(int)e[6]);
     atomicAdd(q + sz + sy + 1, h | (unsigned)(int)e[7]);
+}
+
+// Tile entry of the lower corner of in-brick cell (x, y, z): 24-bit products.
+__device__ __forceinline__ unsigned cell_index(long long ux, long long uy, long long uz) {
+    return __umul24((unsigned)(uz >> 32), kTBX * kTBY) + __umul24((unsigned)(uy >> 32), kTBX) +
+           (unsigned)(ux >> 32);
 }
 
 // Phase 2 over the queued segments: lane i of wave w takes segments
@@ -597,22 +605,20 @@ __device__ __forceinline__ void march_segments(unsigned long long *tile, const R
         const float gr32 = gr * kInv32;  // exact: a power-of-two scale
         const unsigned hi = gr < 0.0f ? 0xffffffffu : 0u;
         const float a_init = gr < 0.0f ? -1.0f : 0.5f;
-        int cx = (int)(ux >> 32), cy = (int)(uy >> 32), cz = (int)(uz >> 32);
+        unsigned cell = cell_index(ux, uy, uz);
         float acc[8] = {a_init, a_init, a_init, a_init, a_init, a_init, a_init, a_init};
         for (int i = 0; i < cnt; ++i) {
-            const int lx = (int)(ux >> 32), ly = (int)(uy >> 32), lz = (int)(uz >> 32);
+            const unsigned here = cell_index(ux, uy, uz);
             // 2^32 times the trilinear weights of the upper corners
             const float fx = (float)(unsigned)ux, fy = (float)(unsigned)uy, fz = (float)(unsigned)uz;
             ux += dx;
             uy += dy;
             uz += dz;
-            if (lx != cx || ly != cy || lz != cz) {
-                flush_cell(tile, cx, cy, cz, acc, hi);
+            if (here != cell) {
+                flush_cell(tile, cell, acc, hi);
 #pragma unroll
                 for (int c = 0; c < 8; ++c) acc[c] = a_init;
-                cx = lx;
-                cy = ly;
-                cz = lz;
+                cell = here;
             }
             // Every corner value is a product of gr and non-negative factors,
             // added with an explicit fma, so it has the sign of gr whatever
@@ -632,7 +638,7 @@ __device__ __forceinline__ void march_segments(unsigned long long *tile, const R
             acc[6] = fmaf(y11, ox, acc[6]);
             acc[7] = fmaf(y11, wx, acc[7]);
         }
-        flush_cell(tile, cx, cy, cz, acc, hi);
+        flush_cell(tile, cell, acc, hi);
     }
 }
 
