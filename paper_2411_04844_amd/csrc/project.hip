@@ -576,9 +576,12 @@ __device__ __forceinline__ void march_segments(unsigned long long *tile, const R
     // rarely add into the same LDS word at once.  (Strides 2 ... 64 were
     // timed; on 16^3 bricks 8 gave the fewest LDS bank conflicts, 3 % faster
     // than 32; on the flat bricks 4 ... 16 are within 0.5 %.)
+    // The last, partial block of 256 is taken in order instead, so waves
+    // beyond its segments skip it and leave their issue slots to the other
+    // work-groups of the CU.
     const int perm = ((t & 31) << 3) | (t >> 5);
     for (int base = 0; base < nsegs; base += 256) {
-        const int s = base + perm;
+        const int s = base + (nsegs - base >= 256 ? perm : t);
         if (s >= nsegs) continue;
         const unsigned e = segs[s];
         const RayRec rec = rays[e >> 3];
