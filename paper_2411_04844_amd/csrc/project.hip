@@ -255,11 +255,12 @@ __device__ __forceinline__ void march_span(const float *vol, int sy, int sz, con
     }
 }
 
-// march_span over the LDS box: the tap index (cells within the box, so every
-// term is below 2^24) takes two 24-bit multiply-adds per sample instead of
-// two full-width multiplies.
+// march_span over the LDS box: the tap's byte offset (cells within the box, so
+// every term is below 2^24) takes two 24-bit multiplies per sample instead of
+// two full-width multiplies and a scaling of each term.
 __device__ __forceinline__ void march_box(const float *box, int sy, int sz, const int o[3], const Ray &r,
                                           int a, int e, float &acc) {
+    const unsigned sy4 = 4u * (unsigned)sy, sz4 = 4u * (unsigned)sz;  // byte strides
     long long ux = r.U[0] + (long long)a * r.DU[0] - ((long long)o[0] << 32);
     long long uy = r.U[1] + (long long)a * r.DU[1] - ((long long)o[1] << 32);
     long long uz = r.U[2] + (long long)a * r.DU[2] - ((long long)o[2] << 32);
@@ -268,8 +269,9 @@ __device__ __forceinline__ void march_box(const float *box, int sy, int sz, cons
         const float wx = (float)(unsigned)ux * kInv32;
         const float wy = (float)(unsigned)uy * kInv32;
         const float wz = (float)(unsigned)uz * kInv32;
-        const unsigned idx = __umul24((unsigned)lz, (unsigned)sz) + __umul24((unsigned)ly, (unsigned)sy) + (unsigned)lx;
-        acc += trilinear(box + idx, sy, sz, wx, wy, wz);
+        const unsigned off = __umul24((unsigned)lz, sz4) + __umul24((unsigned)ly, sy4) + ((unsigned)lx << 2);
+        acc += trilinear(reinterpret_cast<const float *>(reinterpret_cast<const char *>(box) + off), sy, sz, wx,
+                         wy, wz);
         ux += r.DU[0];
         uy += r.DU[1];
         uz += r.DU[2];
