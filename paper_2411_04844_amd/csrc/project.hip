@@ -278,16 +278,31 @@ __device__ __forceinline__ void march_box(const float *box, int sy, int sz, cons
     }
 }
 
+// Minimum / maximum over the 64 lanes of a wave (all lanes active), returned
+// wave-uniform: DPP exchanges within each row of 16 lanes (lane ^ 1, lane ^ 2,
+// then the mirrored lane of the half row and of the row), then the four rows'
+// lane 0 through readlane.  No LDS traffic, unlike a shuffle.
+__device__ __forceinline__ int row_dpp(int v, int ctrl) {
+    switch (ctrl) {  // the control must be a constant
+        case 0: return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+        case 1: return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+        case 2: return __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+        default: return __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false); // row_mirror
+    }
+}
+
 __device__ __forceinline__ int wave_min(int v) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-    return v;
+    for (int c = 0; c < 4; ++c) v = min(v, row_dpp(v, c));
+    return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+               min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 
 __device__ __forceinline__ int wave_max(int v) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    return v;
+    for (int c = 0; c < 4; ++c) v = max(v, row_dpp(v, c));
+    return max(max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+               max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 
 __device__ __forceinline__ float wave_sum(float v) {
