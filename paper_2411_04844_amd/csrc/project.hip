@@ -544,14 +544,19 @@ __device__ __forceinline__ bool in_brick(long long x, long long y, long long z) 
            (unsigned long long)z < ((unsigned long long)kBZ << 32);
 }
 
-__device__ __forceinline__ int wave_excl_scan(int v, int lane, int *total) {
+// Exclusive prefix sum over the 64 lanes of a wave (all lanes active) and the
+// wave total: a Hillis-Steele scan within each row of 16 lanes by DPP row
+// shifts (lanes shifted in from outside the row add 0), then the row totals
+// carried across rows by the DPP row broadcasts of lanes 15 and 31.
+__device__ __forceinline__ int wave_excl_scan(int v, int *total) {
     int incl = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int n = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += n;
-    }
-    *total = __shfl(incl, 63, 64);
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x111, 0xF, 0xF, false);  // row_shr:1
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x112, 0xF, 0xF, false);  // row_shr:2
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x114, 0xF, 0xF, false);  // row_shr:4
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x118, 0xF, 0xF, false);  // row_shr:8
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x142, 0xA, 0xF, false);  // row_bcast:15 -> rows 1, 3
+    incl += __builtin_amdgcn_update_dpp(0, incl, 0x143, 0xC, 0xF, false);  // row_bcast:31 -> rows 2, 3
+    *total = __builtin_amdgcn_readlane(incl, 63);
     return incl - v;
 }
 
@@ -761,14 +766,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
             const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
                                                        __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
             int seg_tot;
-            const int seg_pre = wave_excl_scan(nseg, lane, &seg_tot);
+            const int seg_pre = wave_excl_scan(nseg, &seg_tot);
             int rbase = 0, sbase = 0;
             if (lane == 0 && mask != 0ull) {
                 rbase = atomicAdd(&q_rays, __popcll(mask));
                 sbase = atomicAdd(&q_segs, seg_tot);
             }
-            rbase = __shfl(rbase, 0, 64);
-            sbase = __shfl(sbase, 0, 64);
+            rbase = __builtin_amdgcn_readlane(rbase, 0);
+            sbase = __builtin_amdgcn_readlane(sbase, 0);
             if (n > 0) {
                 const int slot = rbase + rank;
                 rays[slot] = rec;
