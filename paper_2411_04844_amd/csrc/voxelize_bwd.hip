@@ -18,10 +18,26 @@
 namespace dgr {
 namespace {
 
+// Sum over the 64 lanes of a wave (all lanes active), wave-uniform: DPP
+// exchanges within each row of 16 lanes (lane ^ 1, lane ^ 2, then the mirrored
+// lane of the half row and of the row), then the four row sums through
+// readlane.  No LDS traffic, unlike a shuffle.
+__device__ __forceinline__ float row_xchg(float v, int c) {
+    const int b = __float_as_int(v);
+    switch (c) {  // the control must be a constant
+        case 0: return __int_as_float(__builtin_amdgcn_mov_dpp(b, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+        case 1: return __int_as_float(__builtin_amdgcn_mov_dpp(b, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+        case 2: return __int_as_float(__builtin_amdgcn_mov_dpp(b, 0x141, 0xF, 0xF, false));  // row_half_mirror
+        default: return __int_as_float(__builtin_amdgcn_mov_dpp(b, 0x140, 0xF, 0xF, false)); // row_mirror
+    }
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    for (int c = 0; c < 4; ++c) v += row_xchg(v, c);
+    const int b = __float_as_int(v);
+    return (__int_as_float(__builtin_amdgcn_readlane(b, 0)) + __int_as_float(__builtin_amdgcn_readlane(b, 16))) +
+           (__int_as_float(__builtin_amdgcn_readlane(b, 32)) + __int_as_float(__builtin_amdgcn_readlane(b, 48)));
 }
 
 __global__ __launch_bounds__(256) void voxelize_grad(
