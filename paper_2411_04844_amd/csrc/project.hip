@@ -181,8 +181,12 @@ __device__ bool k_interval(const Ray &r, const double lo[3], const double hi[3],
     return true;
 }
 
-// A superset of the samples with lo <= u_a <= hi, from binary32 reciprocals and
-// widened by one sample on each side; callers test every sample exactly.
+// A superset of the samples with lo <= u_a <= hi, from binary32 reciprocals;
+// callers test the end samples exactly.  The binary32 sample parameter t has a
+// relative error below 5 * 2^-24 (offset and advance rounded to binary32, the
+// hardware reciprocal within one ulp, the product rounded); the interval is
+// widened by four times that plus 2^-10.  An axis with no advance only gets a
+// loose band test here: callers test such an axis exactly in fixed point.
 __device__ bool k_interval_coarse(const Ray &r, const double lo[3], const double hi[3], int *k0,
                                   int *k1) {
     float tmin = -3.0e38f, tmax = 3.0e38f;
@@ -201,8 +205,7 @@ __device__ bool k_interval_coarse(const Ray &r, const double lo[3], const double
         tmin = fmaxf(tmin, fminf(t0, t1));
         tmax = fminf(tmax, fmaxf(t0, t1));
     }
-    // relative error of the binary32 interval is below 1e-6 of |t|
-    const float slack = 1.0f + 2e-6f * fmaxf(fabsf(tmin), fabsf(tmax));
+    const float slack = 0x1p-10f + 1.2e-6f * fmaxf(fabsf(tmin), fabsf(tmax));
     tmin -= slack;
     tmax += slack;
     if (!(tmin <= tmax) || tmin < -(float)kMaxK || tmax > (float)kMaxK) return false;
@@ -722,7 +725,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
                 int k0, k1;
                 ray_geom(G, g, j, iu, iv, r);
                 const float gr = gs * pv;
-                if (gr != 0.0f) {
+                // an axis without advance keeps one fixed-point cell for every
+                // sample: test it once (the interval search cannot bound it)
+                const bool still_ok =
+                    (r.DU[0] != 0 || (unsigned long long)(r.U[0] - C0x) < ((unsigned long long)kBX << 32)) &&
+                    (r.DU[1] != 0 || (unsigned long long)(r.U[1] - C0y) < ((unsigned long long)kBY << 32)) &&
+                    (r.DU[2] != 0 || (unsigned long long)(r.U[2] - C0z) < ((unsigned long long)kBZ << 32));
+                if (gr != 0.0f && still_ok) {
                     if (k_interval_coarse(r, blo, bhi, &k0, &k1)) {
                         long long ux = r.U[0] + (long long)k0 * r.DU[0] - C0x;
                         long long uy = r.U[1] + (long long)k0 * r.DU[1] - C0y;
