@@ -346,6 +346,42 @@ __device__ __forceinline__ void block_bounds(int v[6], int (*red)[8], int wave, 
     for (int i = 3; i < 6; ++i) v[i] = max(max(red[0][i], red[1][i]), max(red[2][i], red[3][i]));
 }
 
+// Copies the box of nx x ny x nz padded voxels at src (strides px, plane) into
+// LDS, dense with x fastest.  Box element q is cell (q mod nx, (q / nx) mod
+// ny, q / (nx ny)); the quotients come from binary32 reciprocals, exact here:
+// (q + 1/2) / n_a lies at least 1/(2 n_a) from an integer and its rounding
+// error (reciprocal and fused product) is below (q + 1/2) / n_a * 2^-23,
+// smaller for q < 2^22.  Offsets are 32-bit (the padded copy holds fewer than
+// 2^31 voxels); kSmall: the padded plane is below 2^24 voxels, so their
+// products take 24-bit multiplies.  Each thread issues kStage loads before its
+// first LDS write, so the loads overlap.
+template <bool kSmall>
+__device__ __forceinline__ void stage_box(float *box, const float *__restrict__ src, int nx, int ny, int nz,
+                                          unsigned px, unsigned plane) {
+    const int n = nx * ny * nz;
+    const float inx = 1.0f / (float)nx, iny = 1.0f / (float)ny;
+    const float hnx = 0.5f * inx, hny = 0.5f * iny;  // exact halves
+    constexpr int kStage = 4;
+    for (int q0 = threadIdx.x; q0 < n; q0 += 256 * kStage) {
+        float v[kStage];
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int q = q0 + u * 256;
+            if (q < n) {
+                const int rq = (int)fmaf((float)q, inx, hnx);
+                const int lz = (int)fmaf((float)rq, iny, hny);
+                const int lx = q - __mul24(rq, nx), ly = rq - __mul24(lz, ny);
+                const unsigned off = kSmall ? __umul24((unsigned)lz, plane) + __umul24((unsigned)ly, px) + (unsigned)lx
+                                            : (unsigned)lz * plane + (unsigned)ly * px + (unsigned)lx;
+                v[u] = src[off];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kStage; ++u)
+            if (q0 + u * 256 < n) box[q0 + u * 256] = v[u];
+    }
+}
+
 template <int MODE>
 __global__ __launch_bounds__(256) void project_bundles(const float *__restrict__ vp, PadDims p, DevGrid g,
                                                        GeomDev G, int tiles_u, int tiles_v, int64_t nb,
@@ -401,32 +437,12 @@ __global__ __launch_bounds__(256) void project_bundles(const float *__restrict__
         const int nx = bb[3] - bb[0] + 2, ny = bb[4] - bb[1] + 2, nz = bb[5] - bb[2] + 2;
         if ((int64_t)nx * ny * nz <= kBoxCap) {
             // taps of the chunk: padded voxels o .. o + n - 1, inside the padded
-            // copy.  Box element q is cell (q mod nx, (q / nx) mod ny,
-            // q / (nx ny)); the quotients come from binary32 reciprocals, exact
-            // here: (q + 1/2) / n_a lies at least 1/(2 n_a) from an integer and
-            // its rounding error is below (q + 1/2) / n_a * 2^-23, smaller for
-            // q < 2^22.  Each thread issues kStage loads before its first LDS
-            // write, so the loads overlap.
-            const int n = nx * ny * nz;
-            const float inx = 1.0f / (float)nx, iny = 1.0f / (float)ny;
+            // copy
             const float *src = vp + ((int64_t)o[2] * p.py + o[1]) * p.px + o[0];
-            constexpr int kStage = 4;
-            for (int q0 = t; q0 < n; q0 += 256 * kStage) {
-                float v[kStage];
-#pragma unroll
-                for (int u = 0; u < kStage; ++u) {
-                    const int q = q0 + u * 256;
-                    if (q < n) {
-                        const int rq = (int)(((float)q + 0.5f) * inx);
-                        const int lz = (int)(((float)rq + 0.5f) * iny);
-                        const int lx = q - rq * nx, ly = rq - lz * ny;
-                        v[u] = src[(int64_t)lz * p.plane + ly * p.px + lx];
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < kStage; ++u)
-                    if (q0 + u * 256 < n) box[q0 + u * 256] = v[u];
-            }
+            if (p.plane < (int64_t(1) << 24))
+                stage_box<true>(box, src, nx, ny, nz, (unsigned)p.px, (unsigned)p.plane);
+            else
+                stage_box<false>(box, src, nx, ny, nz, (unsigned)p.px, (unsigned)p.plane);
             __syncthreads();
             if (has) march_box(box, nx, nx * ny, o, r, a, e, acc);
             __syncthreads();
