@@ -540,8 +540,9 @@ __device__ __forceinline__ float fixed_scale(const unsigned *maxbits, float scal
 //     lane runs (nearly) the same number of samples whatever the chord lengths
 //     of the rays, and add the eight weighted values of each sample, in fixed
 //     point, into the LDS tile.
-// The queue spans views; it is drained when it may not hold another chunk
-// (with 320 ray slots that is after nearly every chunk of 256 candidates).
+// The queue holds one chunk of 256 candidates and is drained after it; each
+// wave sets up its rays of the next chunk as soon as its part of the drain is
+// done, while the other waves still march.
 constexpr int kChunk = 256;     // candidates per set-up pass (one per thread)
 constexpr int kRayCap = 320;    // queued rays
 constexpr int kSegCap = 2048;   // queued segments (>= kChunk * kMaxSeg)
@@ -721,107 +722,119 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
         q_segs = 0;
     }
     __syncthreads();
-    ushort4 rc_next = rect[b];
-    for (int j = 0; j < G.n_views; ++j) {
-        const ushort4 rc = rc_next;
-        if (j + 1 < G.n_views) rc_next = rect[(int64_t)(j + 1) * nb + b];  // prefetch
-        const int nu_r = (int)rc.y - (int)rc.x + 1, nv_r = (int)rc.w - (int)rc.z + 1;
-        const int ncand = (nu_r > 0 && nv_r > 0) ? nu_r * nv_r : 0;
-        for (int cb = 0; cb < ncand; cb += kChunk) {
-            // ---- phase 1: one candidate ray per thread (consecutive pixels of
-            // the rectangle, so the projection reads coalesce).  The read is
-            // issued first; the ray set-up hides its latency.
-            const int c = cb + t;
-            int n = 0;
-            RayRec rec;
-            if (c < ncand) {
-                const int iv = (int)rc.z + c / nu_r, iu = (int)rc.x + c % nu_r;
-                const float pv = proj[((int64_t)j * G.nv + iv) * G.nu + iu];
-                Ray r;
-                int k0, k1;
-                ray_geom(G, g, j, iu, iv, r);
-                const float gr = gs * pv;
-                // an axis without advance keeps one fixed-point cell for every
-                // sample: test it once (the interval search cannot bound it)
-                const bool still_ok =
-                    (r.DU[0] != 0 || (unsigned long long)(r.U[0] - C0x) < ((unsigned long long)kBX << 32)) &&
-                    (r.DU[1] != 0 || (unsigned long long)(r.U[1] - C0y) < ((unsigned long long)kBY << 32)) &&
-                    (r.DU[2] != 0 || (unsigned long long)(r.U[2] - C0z) < ((unsigned long long)kBZ << 32));
-                if (gr != 0.0f && still_ok) {
-                    if (k_interval_coarse(r, blo, bhi, &k0, &k1)) {
-                        long long ux = r.U[0] + (long long)k0 * r.DU[0] - C0x;
-                        long long uy = r.U[1] + (long long)k0 * r.DU[1] - C0y;
-                        long long uz = r.U[2] + (long long)k0 * r.DU[2] - C0z;
-                        while (k0 <= k1 && !in_brick(ux, uy, uz)) {
-                            ++k0;
-                            ux += r.DU[0];
-                            uy += r.DU[1];
-                            uz += r.DU[2];
-                        }
-                        if (k0 <= k1) {
-                            long long vx = r.U[0] + (long long)k1 * r.DU[0] - C0x;
-                            long long vy = r.U[1] + (long long)k1 * r.DU[1] - C0y;
-                            long long vz = r.U[2] + (long long)k1 * r.DU[2] - C0z;
-                            while (!in_brick(vx, vy, vz)) {  // stops at k0 at the latest
-                                --k1;
-                                vx -= r.DU[0];
-                                vy -= r.DU[1];
-                                vz -= r.DU[2];
-                            }
-                            n = k1 - k0 + 1;
-                            rec.ulo[0] = (unsigned)ux;
-                            rec.ulo[1] = (unsigned)uy;
-                            rec.ulo[2] = (unsigned)uz;
-                            rec.dlo[0] = (unsigned)r.DU[0];
-                            rec.dlo[1] = (unsigned)r.DU[1];
-                            rec.dlo[2] = (unsigned)r.DU[2];
-                            rec.gr = gr;
-                            rec.meta = (unsigned)(ux >> 32) | ((unsigned)(uy >> 32) << 5) |
-                                       ((unsigned)(uz >> 32) << 10) |
-                                       (((unsigned)(r.DU[0] >> 32) & 7u) << 15) |
-                                       (((unsigned)(r.DU[1] >> 32) & 7u) << 18) |
-                                       (((unsigned)(r.DU[2] >> 32) & 7u) << 21) |
-                                       ((unsigned)(n - 1) << 24);
-                        }
+    // Ray set-up (phase 1) of candidate c of view j's rectangle rc: the
+    // record and the number of the ray's samples in the brick (0: none).
+    auto setup = [&](int j, const ushort4 &rc, int c, RayRec &rec) -> int {
+        const int nu_r = (int)rc.y - (int)rc.x + 1;
+        int n = 0;
+        const int iv = (int)rc.z + c / nu_r, iu = (int)rc.x + c % nu_r;
+        const float pv = proj[((int64_t)j * G.nv + iv) * G.nu + iu];
+        Ray r;
+        int k0, k1;
+        ray_geom(G, g, j, iu, iv, r);
+        const float gr = gs * pv;
+        // an axis without advance keeps one fixed-point cell for every
+        // sample: test it once (the interval search cannot bound it)
+        const bool still_ok =
+            (r.DU[0] != 0 || (unsigned long long)(r.U[0] - C0x) < ((unsigned long long)kBX << 32)) &&
+            (r.DU[1] != 0 || (unsigned long long)(r.U[1] - C0y) < ((unsigned long long)kBY << 32)) &&
+            (r.DU[2] != 0 || (unsigned long long)(r.U[2] - C0z) < ((unsigned long long)kBZ << 32));
+        if (gr != 0.0f && still_ok) {
+            if (k_interval_coarse(r, blo, bhi, &k0, &k1)) {
+                long long ux = r.U[0] + (long long)k0 * r.DU[0] - C0x;
+                long long uy = r.U[1] + (long long)k0 * r.DU[1] - C0y;
+                long long uz = r.U[2] + (long long)k0 * r.DU[2] - C0z;
+                while (k0 <= k1 && !in_brick(ux, uy, uz)) {
+                    ++k0;
+                    ux += r.DU[0];
+                    uy += r.DU[1];
+                    uz += r.DU[2];
+                }
+                if (k0 <= k1) {
+                    long long vx = r.U[0] + (long long)k1 * r.DU[0] - C0x;
+                    long long vy = r.U[1] + (long long)k1 * r.DU[1] - C0y;
+                    long long vz = r.U[2] + (long long)k1 * r.DU[2] - C0z;
+                    while (!in_brick(vx, vy, vz)) {  // stops at k0 at the latest
+                        --k1;
+                        vx -= r.DU[0];
+                        vy -= r.DU[1];
+                        vz -= r.DU[2];
                     }
+                    n = k1 - k0 + 1;
+                    rec.ulo[0] = (unsigned)ux;
+                    rec.ulo[1] = (unsigned)uy;
+                    rec.ulo[2] = (unsigned)uz;
+                    rec.dlo[0] = (unsigned)r.DU[0];
+                    rec.dlo[1] = (unsigned)r.DU[1];
+                    rec.dlo[2] = (unsigned)r.DU[2];
+                    rec.gr = gr;
+                    rec.meta = (unsigned)(ux >> 32) | ((unsigned)(uy >> 32) << 5) |
+                               ((unsigned)(uz >> 32) << 10) |
+                               (((unsigned)(r.DU[0] >> 32) & 7u) << 15) |
+                               (((unsigned)(r.DU[1] >> 32) & 7u) << 18) |
+                               (((unsigned)(r.DU[2] >> 32) & 7u) << 21) |
+                               ((unsigned)(n - 1) << 24);
                 }
-            }
-            const int nseg = (n + seg_len - 1) / seg_len;
-            const unsigned long long mask = __ballot(n > 0);
-            const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
-                                                       __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
-            int seg_tot;
-            const int seg_pre = wave_excl_scan(nseg, &seg_tot);
-            int rbase = 0, sbase = 0;
-            if (lane == 0 && mask != 0ull) {
-                rbase = atomicAdd(&q_rays, __popcll(mask));
-                sbase = atomicAdd(&q_segs, seg_tot);
-            }
-            rbase = __builtin_amdgcn_readlane(rbase, 0);
-            sbase = __builtin_amdgcn_readlane(sbase, 0);
-            if (n > 0) {
-                const int slot = rbase + rank;
-                rays[slot] = rec;
-                for (int q = 0; q < nseg; ++q) segs[sbase + seg_pre + q] = (unsigned short)((slot << 3) | q);
-            }
-            __syncthreads();
-            const int nr = q_rays, ns = q_segs;
-            __syncthreads();  // every thread has read the counts before they change
-            if (nr > kRayCap - kChunk || ns > kSegCap - kChunk * kMaxSeg) {
-                // ---- phase 2
-                march_segments(tile, rays, segs, ns, seg_len);
-                __syncthreads();
-                if (t == 0) {
-                    q_rays = 0;
-                    q_segs = 0;
-                }
-                __syncthreads();
             }
         }
+        return n;
+    };
+    // The candidates of all views are taken 256 at a time (one per thread;
+    // consecutive pixels of a rectangle, so the projection reads coalesce):
+    // the chunk starting at candidate cb of view j.  advance() moves to the
+    // next chunk, skipping empty rectangles; j == n_views when done.
+    int j = -1, cb = -kChunk, ncand = 0;
+    ushort4 rc = make_ushort4(1, 0, 1, 0), rc_next = rect[b];
+    auto advance = [&]() {
+        cb += kChunk;
+        while (cb >= ncand) {
+            if (++j >= G.n_views) return;
+            rc = rc_next;
+            if (j + 1 < G.n_views) rc_next = rect[(int64_t)(j + 1) * nb + b];  // prefetch
+            const int nu_r = (int)rc.y - (int)rc.x + 1, nv_r = (int)rc.w - (int)rc.z + 1;
+            ncand = (nu_r > 0 && nv_r > 0) ? nu_r * nv_r : 0;
+            cb = 0;
+        }
+    };
+    RayRec rec;
+    int n = 0;
+    advance();
+    if (j < G.n_views && cb + t < ncand) n = setup(j, rc, cb + t, rec);
+    while (j < G.n_views) {
+        // ---- queue the chunk's rays and segments (the queue is empty)
+        const int nseg = (n + seg_len - 1) / seg_len;
+        const unsigned long long mask = __ballot(n > 0);
+        const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                                   __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+        int seg_tot;
+        const int seg_pre = wave_excl_scan(nseg, &seg_tot);
+        int rbase = 0, sbase = 0;
+        if (lane == 0 && mask != 0ull) {
+            rbase = atomicAdd(&q_rays, __popcll(mask));
+            sbase = atomicAdd(&q_segs, seg_tot);
+        }
+        rbase = __builtin_amdgcn_readlane(rbase, 0);
+        sbase = __builtin_amdgcn_readlane(sbase, 0);
+        if (n > 0) {
+            const int slot = rbase + rank;
+            rays[slot] = rec;
+            for (int q = 0; q < nseg; ++q) segs[sbase + seg_pre + q] = (unsigned short)((slot << 3) | q);
+        }
+        __syncthreads();
+        const int ns = q_segs;
+        // ---- phase 2; then each wave sets up its rays of the next chunk
+        // while the other waves finish their segments
+        march_segments(tile, rays, segs, ns, seg_len);
+        advance();
+        n = 0;
+        if (j < G.n_views && cb + t < ncand) n = setup(j, rc, cb + t, rec);
+        __syncthreads();
+        if (t == 0) {
+            q_rays = 0;
+            q_segs = 0;
+        }
+        __syncthreads();
     }
-    const int ns = q_segs;
-    if (ns > 0) march_segments(tile, rays, segs, ns, seg_len);
-    __syncthreads();
     long long *out = staging + b * kBT3;
     for (int e = t; e < kBT3; e += 256) out[e] = (long long)tile[e];
 }
