@@ -610,7 +610,7 @@ __device__ __forceinline__ unsigned cell_index(long long ux, long long uy, long 
 // cell visit.  The fixed-point scale leaves room for the largest number of
 // samples one cell can hold.
 __device__ __forceinline__ void march_segments(unsigned long long *tile, const RayRec *rays,
-                                               const unsigned short *segs, int nsegs, int seg_len) {
+                                               const unsigned short *segs, int nsegs, int seg_shift) {
     const int t = threadIdx.x;
     // Lane order within each block of 256 segments is strided by 8: a ray's
     // segments are queued together and neighbouring pixels one after the
@@ -636,8 +636,8 @@ __device__ __forceinline__ void march_segments(unsigned long long *tile, const R
         const long long dy = (long long)(((unsigned long long)(long long)((int)(m << 11) >> 29) << 32) | rec.dlo[1]);
         const long long dz = (long long)(((unsigned long long)(long long)((int)(m << 8) >> 29) << 32) | rec.dlo[2]);
         const int n = (int)(m >> 24) + 1;
-        const int k_off = seg * seg_len;
-        const int cnt = min(seg_len, n - k_off);
+        const int k_off = seg << seg_shift;
+        const int cnt = min(1 << seg_shift, n - k_off);
         ux += (long long)k_off * dx;
         uy += (long long)k_off * dy;
         uz += (long long)k_off * dz;
@@ -687,15 +687,15 @@ __device__ __forceinline__ void march_segments(unsigned long long *tile, const R
     }
 }
 
-// seg_len: samples per segment, chosen on the host so that no ray in a brick
-// has more than kMaxSeg segments (and no more than 256 samples).
+// seg_shift: log2 of the samples per segment, chosen on the host so that no ray
+// in a brick has more than kMaxSeg segments (and no more than 256 samples).
 // Three work-groups per CU (53 KB of LDS each, <= 168 VGPRs): the extra waves
 // overlap one work-group's LDS adds with another's arithmetic.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void backproject_bricks(const float *__restrict__ proj, DevGrid g,
                                                           GeomDev G, Bricks bk,
                                                           const ushort4 *__restrict__ rect,
                                                           float eps, const unsigned *__restrict__ maxbits,
-                                                          int seg_len, int headroom,
+                                                          int seg_shift, int headroom,
                                                           long long *__restrict__ staging) {
     __shared__ unsigned long long tile[kBT3];
     __shared__ RayRec rays[kRayCap];
@@ -724,10 +724,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     __syncthreads();
     // Ray set-up (phase 1) of candidate c of view j's rectangle rc: the
     // record and the number of the ray's samples in the brick (0: none).
-    auto setup = [&](int j, const ushort4 &rc, int c, RayRec &rec) -> int {
+    auto setup = [&](int j, const ushort4 &rc, float inu, long long c, RayRec &rec) -> int {
         const int nu_r = (int)rc.y - (int)rc.x + 1;
         int n = 0;
-        const int iv = (int)rc.z + c / nu_r, iu = (int)rc.x + c % nu_r;
+        // c / nu_r from a binary32 reciprocal, exact for c < 2^22 (as in the
+        // forward staging); integer division beyond
+        int row, col;
+        if (c < (1 << 22)) {
+            row = (int)fmaf((float)c, inu, 0.5f * inu);
+            col = (int)c - row * nu_r;
+        } else {
+            row = (int)(c / nu_r);
+            col = (int)(c - (long long)row * nu_r);
+        }
+        const int iv = (int)rc.z + row, iu = (int)rc.x + col;
         const float pv = proj[((int64_t)j * G.nv + iv) * G.nu + iu];
         Ray r;
         int k0, k1;
@@ -783,7 +793,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     // consecutive pixels of a rectangle, so the projection reads coalesce):
     // the chunk starting at candidate cb of view j.  advance() moves to the
     // next chunk, skipping empty rectangles; j == n_views when done.
-    int j = -1, cb = -kChunk, ncand = 0;
+    int j = -1;
+    long long cb = -kChunk, ncand = 0;  // a rectangle may hold up to 2^32 pixels
+    float inu = 1.0f;  // 1 / rectangle width
     ushort4 rc = make_ushort4(1, 0, 1, 0), rc_next = rect[b];
     auto advance = [&]() {
         cb += kChunk;
@@ -792,17 +804,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
             rc = rc_next;
             if (j + 1 < G.n_views) rc_next = rect[(int64_t)(j + 1) * nb + b];  // prefetch
             const int nu_r = (int)rc.y - (int)rc.x + 1, nv_r = (int)rc.w - (int)rc.z + 1;
-            ncand = (nu_r > 0 && nv_r > 0) ? nu_r * nv_r : 0;
+            ncand = (nu_r > 0 && nv_r > 0) ? (long long)nu_r * nv_r : 0;
+            inu = nu_r > 0 ? 1.0f / (float)nu_r : 1.0f;
             cb = 0;
         }
     };
     RayRec rec;
     int n = 0;
     advance();
-    if (j < G.n_views && cb + t < ncand) n = setup(j, rc, cb + t, rec);
+    if (j < G.n_views && cb + t < ncand) n = setup(j, rc, inu, cb + t, rec);
     while (j < G.n_views) {
         // ---- queue the chunk's rays and segments (the queue is empty)
-        const int nseg = (n + seg_len - 1) / seg_len;
+        const int nseg = (n + (1 << seg_shift) - 1) >> seg_shift;
         const unsigned long long mask = __ballot(n > 0);
         const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
                                                    __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
@@ -824,10 +837,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
         const int ns = q_segs;
         // ---- phase 2; then each wave sets up its rays of the next chunk
         // while the other waves finish their segments
-        march_segments(tile, rays, segs, ns, seg_len);
+        march_segments(tile, rays, segs, ns, seg_shift);
         advance();
         n = 0;
-        if (j < G.n_views && cb + t < ncand) n = setup(j, rc, cb + t, rec);
+        if (j < G.n_views && cb + t < ncand) n = setup(j, rc, inu, cb + t, rec);
         __syncthreads();
         if (t == 0) {
             q_rays = 0;
@@ -1018,7 +1031,8 @@ extern "C" dgr_status dgr_backproject(const float *proj, const dgr_grid *grid,
     const int max_n = (int)std::min(1e9, std::floor(chord * 1.0001 / step_min) + 2.0);
     DGR_CHECK(max_n <= 256, "backprojection needs step >= %.3g voxel (got %.4g)", chord / 254.0, step_min);
     DGR_CHECK((double)geom->step * max_inv <= 3.9, "backprojection needs step <= 3.9 voxels");
-    const int seg_len = std::max(8, (max_n + kMaxSeg - 1) / kMaxSeg);
+    int seg_shift = 3;  // segments of 2^seg_shift samples, at most kMaxSeg of them per ray
+    while ((kMaxSeg << seg_shift) < max_n) ++seg_shift;
     // samples of one ray inside one unit cell: at most sqrt(3) / step + 1
     const int per_cell = (int)std::floor(std::sqrt(3.0) * 1.0001 / step_min) + 1;
     int headroom = 0;
@@ -1041,7 +1055,7 @@ extern "C" dgr_status dgr_backproject(const float *proj, const dgr_grid *grid,
         proj, nproj, w.maxbits);
     DGR_LAUNCH_CHECK();
     backproject_bricks<<<dim3((unsigned)bk.count()), dim3(256), 0, st>>>(proj, g, G, bk, w.rect, eps,
-                                                                         w.maxbits, seg_len, headroom,
+                                                                         w.maxbits, seg_shift, headroom,
                                                                          w.staging);
     DGR_LAUNCH_CHECK();
     const int64_t nvox = (int64_t)grid->dims[0] * grid->dims[1] * grid->dims[2];
