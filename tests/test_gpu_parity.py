@@ -244,6 +244,26 @@ def test_backproject_parity_and_adjoint(kind):
     assert abs(lhs - rhs) <= TOL * np.linalg.norm(Ax) * np.linalg.norm(g)
 
 
+def test_backproject_brick_rectangle_beyond_2_22_candidates():
+    """A 4096 x 1100 detector lying inside the shadow of a brick: the brick's
+    detector rectangle holds 4.5 M candidate pixels, more than the 2^22 up to
+    which the set-up takes pixel rows from a binary32 reciprocal; the rows
+    beyond take the integer path."""
+    say("backproject large rectangle")
+    grid = inputs.GridSpec((20, 20, 10), (-10 / 64, -10 / 64, -5 / 64), (64.0, 64.0, 64.0))
+    geom = inputs.cone_geometry(1, 4096, 1100, 1e-4, 4.0, 6.0, 0.5 / 64, length_scale=1.0)
+    assert geom.nu * geom.nv > 2 ** 22
+    g = np.random.default_rng(97).normal(size=(1, geom.nv, geom.nu)).astype(np.float32)
+    got = native.dgr_backproject(dev(g), grid, geom, dev(geom.views)).cpu().numpy()
+    want = oracle.backproject(g.astype(np.float64), grid.dims, grid.lo, grid.inv_h, geom.kind, geom.views,
+                              geom.nu, geom.nv, geom.step, geom.length_scale)
+    err = rel_l2(got, want)
+    worst = float(np.abs(got.astype(np.float64) - want).max() / np.abs(want).max())
+    say("backproject large rectangle rel_l2", err, "worst voxel / max", worst)
+    assert np.count_nonzero(want) > 0.5 * want.size
+    assert err < TOL and worst < 1e-5
+
+
 def test_project_rays_with_disjoint_sample_ranges():
     """Two rays of one pixel bundle whose sample ranges are far apart
     ([-149, -50] and [50, 149]): the chunks between them hold no sample of
