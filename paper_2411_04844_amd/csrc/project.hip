@@ -644,12 +644,13 @@ __device__ __forceinline__ void march_segments(unsigned long long *tile, const R
         const float gr = rec.gr;
         // Fixed-point conversion: every corner value of a ray has the sign of
         // gr, so the high word of its 64-bit integer is the sign of gr.  The
-        // accumulators start at 0.5 (positive: truncation rounds to nearest)
-        // or -1 (negative: the integer is -1 or less, never 0, which would
-        // need a high word of 0).
+        // accumulators start at +1 or -1, so the truncated integer is at
+        // least 1 or at most -1 (never 0, whose high word would be 0 for
+        // either sign); it lies within one unit of the value, on average half
+        // a unit away from zero, with opposite signs for the two signs of gr.
         const float gr32 = gr * kInv32;  // exact: a power-of-two scale
         const unsigned hi = gr < 0.0f ? 0xffffffffu : 0u;
-        const float a_init = gr < 0.0f ? -1.0f : 0.5f;
+        const float a_init = gr < 0.0f ? -1.0f : 1.0f;
         unsigned cell = cell_index(ux, uy, uz);
         float acc[8] = {a_init, a_init, a_init, a_init, a_init, a_init, a_init, a_init};
         for (int i = 0; i < cnt; ++i) {
