@@ -471,14 +471,25 @@ __global__ __launch_bounds__(256) void project_bundles(const float *__restrict__
 }
 
 // Sum of the work-group partials in binary64, fixed order; loss = sum / M.
-__global__ __launch_bounds__(256) void finish_loss(const float *__restrict__ partial, int64_t nb,
-                                                   double inv_m, float *__restrict__ loss) {
-    __shared__ double s[256];
-    double acc = 0.0;
-    for (int64_t i = threadIdx.x; i < nb; i += 256) acc += (double)partial[i];
-    s[threadIdx.x] = acc;
+// One work-group of 1024 threads; each thread keeps eight independent sums
+// so that eight loads are in flight at a time.
+__global__ __launch_bounds__(1024) void finish_loss(const float *__restrict__ partial, int64_t nb,
+                                                    double inv_m, float *__restrict__ loss) {
+    __shared__ double s[1024];
+    constexpr int kU = 8;
+    double acc[kU] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int64_t i = threadIdx.x;
+    for (; i + (kU - 1) * 1024 < nb; i += kU * 1024) {
+        float p[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) p[u] = partial[i + u * 1024];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) acc[u] += (double)p[u];
+    }
+    for (; i < nb; i += 1024) acc[0] += (double)partial[i];
+    s[threadIdx.x] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
+    for (int o = 512; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
         __syncthreads();
     }
@@ -995,7 +1006,7 @@ static dgr_status project_impl(const float *volume, const dgr_grid *grid, const 
         w.vpad, p, g, geom_dev(geom), tu, tv, nb, target, out, (float)(1.0 / m), w.partial);
     DGR_LAUNCH_CHECK();
     if (MODE == 1) {
-        finish_loss<<<1, 256, 0, st>>>(w.partial, nb, 1.0 / m, loss);
+        finish_loss<<<1, 1024, 0, st>>>(w.partial, nb, 1.0 / m, loss);
         DGR_LAUNCH_CHECK();
     }
     return DGR_OK;
