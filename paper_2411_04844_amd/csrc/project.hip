@@ -546,7 +546,8 @@ __device__ __forceinline__ float fixed_scale(const unsigned *maxbits, float scal
 //  1. Ray set-up: each thread takes one candidate pixel of a view's shadow
 //     rectangle, computes its ray and the exact range [k0, k1] of samples whose
 //     trilinear cell lies in the brick, and appends a 32-byte record to an LDS
-//     queue, plus one entry per segment of at most L consecutive samples.
+//     queue, plus one entry per segment of at most L = 2^seg_shift
+//     consecutive samples.
 //  2. March: the work-group's lanes take the queued segments in order, so every
 //     lane runs (nearly) the same number of samples whatever the chord lengths
 //     of the rays, and add the eight weighted values of each sample, in fixed
@@ -555,7 +556,7 @@ __device__ __forceinline__ float fixed_scale(const unsigned *maxbits, float scal
 // wave sets up its rays of the next chunk as soon as its part of the drain is
 // done, while the other waves still march.
 constexpr int kChunk = 256;     // candidates per set-up pass (one per thread)
-constexpr int kRayCap = 320;    // queued rays
+constexpr int kRayCap = 256;    // queued rays (one chunk)
 constexpr int kSegCap = 2048;   // queued segments (>= kChunk * kMaxSeg)
 constexpr int kMaxSeg = 8;      // segments per ray (the host sizes L for this)
 static_assert(kSegCap >= kChunk * kMaxSeg && kRayCap >= kChunk, "a chunk must fit an empty queue");
@@ -701,7 +702,7 @@ __device__ __forceinline__ void march_segments(unsigned long long *tile, const R
 
 // seg_shift: log2 of the samples per segment, chosen on the host so that no ray
 // in a brick has more than kMaxSeg segments (and no more than 256 samples).
-// Three work-groups per CU (53 KB of LDS each, <= 168 VGPRs): the extra waves
+// Three work-groups per CU (51 KB of LDS each, <= 168 VGPRs): the extra waves
 // overlap one work-group's LDS adds with another's arithmetic.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void backproject_bricks(const float *__restrict__ proj, DevGrid g,
                                                           GeomDev G, Bricks bk,
