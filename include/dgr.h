@@ -170,7 +170,14 @@ dgr_status dgr_project_l1(const float *volume, const dgr_grid *grid, const dgr_g
                           const float *target, float *loss, float *dproj, void *ws,
                           size_t ws_bytes, void *stream);
 
-/* volume [nz][ny][nx] = T^T(proj): the exact transpose of dgr_project. */
+/* volume [nz][ny][nx] = T^T(proj): the exact transpose of dgr_project.
+ * Deterministic: the per-voxel sums are 64-bit fixed point (a power-of-two
+ * scale from max|proj|; each sum of one ray's samples in one cell is rounded
+ * to within one unit, about 2^-27 max|proj| length_scale step at half-voxel
+ * steps), so they do not depend on the order of the adds.  The march step,
+ * in voxels of every axis, must lie between 0.12 and 3.9 (at most 256
+ * samples of one ray in a brick of 20 x 20 x 10 voxels, advances below 4
+ * voxels); DGR_ERR_INVALID_ARG otherwise. */
 dgr_status dgr_backproject(const float *proj, const dgr_grid *grid, const dgr_geometry *geom,
                            float *volume, void *ws, size_t ws_bytes, void *stream);
 
