@@ -33,10 +33,13 @@ What pins each function (tests under ``tests/test_oracle_*.py``):
 * ``voxelize_grad`` -- pinned by binary64 central differences of
   ``voxelize_box`` with frozen boxes, and by d rho = <dL/dV, G>.
 * ``l1``, ``adam``, ``psnr`` -- pinned by hand-computed values and by
-  ``torch.optim.Adam`` on a special case.
+  ``torch.optim.Adam`` (followed by ``clamp_`` for the projected step).
 * ``fdk`` -- pinned by reconstructing a uniform ball from its analytic
-  projections (interior value and exterior zero within a few per cent), and
-  by the discrete Ram-Lak response of a single impulse.
+  projections (interior value and exterior zero within a few per cent), an
+  off-centre ball whose halves nearer and farther from the rotation axis
+  must agree (the distance weights), and by its ramp filter
+  (``ramp_filter``): the impulse response is the textbook tap table, and a
+  cosine row is scaled by |w| / (2 pi tau), the filter's Fourier series.
 * ``init_from_volume`` -- pinned by brute-force inverse-CDF sampling in
   numpy and by the sampling frequencies of a two-voxel volume.
 * ``oracle.unet`` (numpy, binary64) -- the learned-initialisation network:
@@ -104,10 +107,12 @@ def lib():
         L.orc_backproject_siddon.restype = None
         L.orc_l1.argtypes = [P, P, i64, P]
         L.orc_l1.restype = f64
-        L.orc_adam.argtypes = [P, P, P, P, i64, f64, f64, f64, f64, i64]
+        L.orc_adam.argtypes = [P, P, P, P, i64, f64, f64, f64, f64, i64, f64]
         L.orc_adam.restype = None
         L.orc_psnr.argtypes = [P, P, i64]
         L.orc_psnr.restype = f64
+        L.orc_ramp_filter.argtypes = [P, i64, f64, P]
+        L.orc_ramp_filter.restype = None
         L.orc_fdk.argtypes = [P, i32, i32, i32, i32, P, f64, f64, P, P, P, P]
         L.orc_fdk.restype = None
         L.orc_init_from_volume.argtypes = [P, P, P, P, f64, i64, P, f64, P, P, P, P, P]
@@ -244,13 +249,22 @@ def l1(proj, target):
     return float(loss), g
 
 
-def adam(p, g, m, v, lr, t, b1=0.9, b2=0.999, eps=1e-8):
-    """One Adam step in place on float64 arrays p, m, v."""
+def adam(p, g, m, v, lr, t, b1=0.9, b2=0.999, eps=1e-8, lower=-np.inf):
+    """One Adam step in place on float64 arrays p, m, v, projected onto
+    p >= lower (-inf: the plain step)."""
     for a in (p, m, v):
         assert a.dtype == np.float64 and a.flags.c_contiguous
     g = _c(g, np.float64)
     lib().orc_adam(_p(p), _p(g), _p(m), _p(v), p.size, float(lr), float(b1), float(b2),
-                   float(eps), int(t))
+                   float(eps), int(t), float(lower))
+
+
+def ramp_filter(p, tau):
+    """The FDK step's discrete Ram-Lak filter of one row (float64)."""
+    p = _c(p, np.float64)
+    q = np.zeros_like(p)
+    lib().orc_ramp_filter(_p(p), p.size, float(tau), _p(q))
+    return q
 
 
 def fdk(proj, views, nu, nv, arc, length_scale, dims, lo, inv_h, kind=1):

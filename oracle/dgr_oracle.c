@@ -659,18 +659,23 @@ double orc_l1(const double *proj, const float *target, int64_t m, double *g)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Adam step (the optimiser of sec. 5.1, Implementation Details):            */
+/* Adam step (the optimiser of sec. 5.1, Implementation Details), projected */
+/* onto p >= lower (the reconstruction keeps densities in R+, sec. 4.1, and */
+/* scales positive):                                                        */
 /*   m <- b1 m + (1-b1) g,  v <- b2 v + (1-b2) g^2,                         */
-/*   p <- p - lr * (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps).             */
+/*   p <- max(p - lr * (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps), lower). */
+/* The moments are not affected by the projection.  lower = -inf gives the  */
+/* plain step.                                                              */
 /* ------------------------------------------------------------------------ */
 void orc_adam(double *p, const double *g, double *m, double *v, int64_t n, double lr, double b1,
-              double b2, double eps, int64_t t)
+              double b2, double eps, int64_t t, double lower)
 {
     double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);
     for (int64_t i = 0; i < n; ++i) {
         m[i] = b1 * m[i] + (1.0 - b1) * g[i];
         v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
-        p[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
+        double next = p[i] - lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
+        p[i] = next < lower ? lower : next;
     }
 }
 
@@ -732,6 +737,24 @@ static void view_frame(const float *v, double s[3], double det[3], double eu[3],
     *R = -(s[0] * n[0] + s[1] * n[1] + s[2] * n[2]);
 }
 
+/* Step 2 alone: the discrete Ram-Lak filter of one row p[nu] with sample  */
+/* spacing tau, the samples of the band-limited ramp |w| (Kak & Slaney,     */
+/* ch. 3): h(0) = 1/(4 tau^2), h(k) = 0 for even k != 0 and                 */
+/* -1/(k^2 pi^2 tau^2) for odd k, convolved with spacing tau; samples       */
+/* beyond the row are zero.                                                 */
+void orc_ramp_filter(const double *p, int64_t nu, double tau, double *q)
+{
+    for (int64_t i = 0; i < nu; ++i) {
+        double acc = 0.25 * p[i];
+        for (int64_t k = 1; k < nu; k += 2) {
+            double w = 1.0 / ((double)k * (double)k * M_PI * M_PI);
+            if (i - k >= 0) acc -= w * p[i - k];
+            if (i + k < nu) acc -= w * p[i + k];
+        }
+        q[i] = acc / tau;
+    }
+}
+
 void orc_fdk(const float *proj, int32_t kind, int32_t n_views, int32_t nu, int32_t nv, const float *views,
              double arc, double length_scale, const int32_t dims[3], const double glo[3],
              const double inv_h[3], double *V)
@@ -756,15 +779,7 @@ void orc_fdk(const float *proj, int32_t kind, int32_t n_views, int32_t nu, int32
             }
             row[iu] = (double)proj[(j * nv + iv) * nu + iu] * D / sqrt(r2);
         }
-        for (int64_t i = 0; i < nu; ++i) {
-            double acc = 0.25 * row[i];
-            for (int64_t k = 1; k < nu; k += 2) {
-                double w = 1.0 / ((double)k * (double)k * M_PI * M_PI);
-                if (i - k >= 0) acc -= w * row[i - k];
-                if (i + k < nu) acc -= w * row[i + k];
-            }
-            q[(j * nv + iv) * nu + i] = acc / tau;
-        }
+        orc_ramp_filter(row, nu, tau, q + (j * nv + iv) * nu);
         free(row);
     }
     double dbeta = arc / (double)n_views;

@@ -348,19 +348,29 @@ def test_voxelize_backward_parity(gname):
     assert np.all(got[2][0].cpu().numpy() == 0.0)
 
 
-def test_adam_parity():
-    say("adam")
+@pytest.mark.parametrize("lower", [-np.inf, 0.0, -0.25])
+def test_adam_parity(lower):
+    """The (projected) Adam step against the oracle.  With a finite bound a
+    good share of the entries start at or just above it and get gradients
+    that push them into it, so the clamp is exercised every step."""
+    say("adam", "lower", lower)
     rng = np.random.default_rng(8)
-    p0 = rng.normal(size=5000).astype(np.float32)
-    p, m, v = dev(p0), torch.zeros(5000, device="cuda"), torch.zeros(5000, device="cuda")
-    P, M, Vv = p0.astype(np.float64), np.zeros(5000), np.zeros(5000)
+    n = 5000
+    p0 = rng.normal(size=n).astype(np.float32)
+    if np.isfinite(lower):
+        p0[:1500] = np.float32(lower) + rng.uniform(0, 2e-3, size=1500).astype(np.float32)
+        p0[:500] = np.float32(lower)
+        p0 = np.maximum(p0, np.float32(lower))
+    p, m, v = dev(p0), torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda")
+    P, M, Vv = p0.astype(np.float64), np.zeros(n), np.zeros(n)
     steps = 5
+    f = lambda x: float(np.float32(x))  # the ABI takes binary32 hyper-parameters
     for t in range(1, steps + 1):
-        g = rng.normal(size=5000).astype(np.float32)
-        native.dgr_adam(p, dev(g), m, v, 1e-3, t)
-        # the ABI takes binary32 hyper-parameters; the oracle gets the same values
-        f = lambda x: float(np.float32(x))
-        oracle.adam(P, g, M, Vv, f(1e-3), t, b1=f(0.9), b2=f(0.999), eps=f(1e-8))
+        g = rng.normal(size=n).astype(np.float32)
+        if np.isfinite(lower):
+            g[:1500] = np.abs(g[:1500])
+        native.dgr_adam(p, dev(g), m, v, 1e-3, t, lower=lower)
+        oracle.adam(P, g, M, Vv, f(1e-3), t, b1=f(0.9), b2=f(0.999), eps=f(1e-8), lower=f(lower))
     # moments agree to binary32 rounding; the parameter differs from the
     # binary64 oracle only by one rounding of the stored value per step
     assert rel_l2(m.cpu().numpy(), M) < 1e-6 and rel_l2(v.cpu().numpy(), Vv) < 1e-6
@@ -369,3 +379,10 @@ def test_adam_parity():
     ulp = np.spacing((np.maximum(np.abs(P), np.abs(p0)) + steps * 1e-3).astype(np.float32)).astype(np.float64)
     assert np.all(np.abs(pg - P) <= steps * ulp)
     assert rel_l2(pg - p0, P - p0) < 1e-4
+    if np.isfinite(lower):
+        at = P == f(lower)
+        assert at.sum() >= 1000, at.sum()
+        # the same entries sit on the bound, up to a binary32 rounding that
+        # lands a step exactly on it (the ulp bound above covers their values)
+        assert int(np.sum((pg == f(lower)) != at)) <= 5
+        assert np.all(pg >= f(lower))

@@ -72,3 +72,26 @@ def test_split_draws_have_the_gaussian_moments():
     assert np.max(np.abs(X.mean(axis=0))) < 5 * 0.05 / np.sqrt(2 * n)
     assert np.max(np.abs(C - Sigma)) < 0.05 * np.max(Sigma)
     np.testing.assert_allclose(P2["scale"][0], s[0] / 2 ** (1 / 3), rtol=1e-6)
+
+
+def test_prune_of_oversized_gaussians():
+    """Alg. 2's prune of Gaussians larger than 3 x size (read as box edges in
+    voxels): at size 17 and 128 voxels per unit the bound is 51/128 = 0.3984.
+    Hand cases just below and above it, and the other two prune reasons
+    (near-zero gradient, non-positive density) left out."""
+    n = 6
+    bound = np.float32(3 * 17) / np.float32(128.0)
+    s = np.full((n, 3), 0.01, np.float32)
+    s[0, 2] = np.nextafter(bound, np.float32(0))  # just below: kept
+    s[1, 0] = bound                               # equal: kept (strictly larger prunes)
+    s[2, 1] = np.nextafter(bound, np.float32(1))  # just above: pruned
+    s[3, :] = 0.5                                  # far above: pruned
+    P = {"mu": np.zeros((n, 3), np.float32), "scale": s,
+         "quat": np.tile(np.array([[1, 0, 0, 0]], np.float32), (n, 1)), "density": np.ones(n, np.float32)}
+    state = {k: (np.zeros_like(v), np.zeros_like(v)) for k, v in P.items()}
+    acc = np.full(n, 1e-6, np.float32)  # avg 1e-8: neither near zero nor enough to clone or split
+    P2, _, info = Dn.densify(P, state, acc, iters=100, normals=np.zeros((n, 2, 3), np.float32), n_max=100,
+                             tau=1e-3, tau_prune=1e-9, theta=0.0173, size_vox=17, inv_h=(128.0,) * 3)
+    assert info["cloned"] == 0 and info["split"] == 0
+    assert list(info["prune"]) == [False, False, True, True, False, False]
+    np.testing.assert_array_equal(P2["scale"], s[[0, 1, 4, 5]])

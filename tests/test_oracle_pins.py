@@ -546,6 +546,36 @@ def test_adam_matches_torch():
     assert np.allclose(p0 - p1, 1e-3 * grads[0] / (np.abs(grads[0]) + 1e-8), atol=1e-16)
 
 
+@pytest.mark.parametrize("lower", [0.0, -0.5])
+def test_projected_adam_matches_torch_then_clamp(lower):
+    """The projected step equals torch.optim.Adam followed by clamp_ onto
+    p >= lower (the moments are not touched by the projection); many entries
+    start at or near the bound so that a good share is clamped."""
+    import torch
+    rng = np.random.default_rng(3)
+    n = 400
+    p0 = np.concatenate([np.full(100, lower), lower + rng.uniform(0, 2e-3, size=100), rng.normal(size=200)])
+    p0 = np.maximum(p0, lower)
+    grads = rng.normal(size=(6, n))
+    grads[:, :150] = np.abs(grads[:, :150])  # pushes those entries down, into the bound
+    t = torch.tensor(p0.copy(), requires_grad=True)
+    opt = torch.optim.Adam([t], lr=1e-3, betas=(0.9, 0.999), eps=1e-8)
+    p, m, v = p0.copy(), np.zeros(n), np.zeros(n)
+    clamped = 0
+    for i in range(6):
+        opt.zero_grad()
+        t.grad = torch.tensor(grads[i])
+        opt.step()
+        with torch.no_grad():
+            clamped += int((t < lower).sum())
+            t.clamp_(min=lower)
+        oracle.adam(p, grads[i], m, v, 1e-3, i + 1, lower=lower)
+        np.testing.assert_allclose(p, t.detach().numpy(), rtol=0, atol=1e-15)
+    assert clamped >= 150
+    assert np.all(p >= lower) and np.sum(p == lower) >= 100
+    np.testing.assert_allclose(m, opt.state[t]["exp_avg"].numpy(), rtol=0, atol=1e-15)
+
+
 def test_psnr_hand_value():
     gt = np.zeros(1000)
     gt[0] = 2.0
