@@ -14,7 +14,9 @@
  * - Memory: every array argument is a DEVICE pointer (HIP), contiguous and
  *   row-major, binary32 unless stated.  The caller allocates and owns every
  *   buffer, including the workspace `ws`; the library keeps no device state
- *   between calls and never allocates device memory.
+ *   between calls and never allocates device memory.  The one exception is
+ *   dgr_voxelize_backward_noalloc, whose records live in a fixed 32 MiB
+ *   device array that each GPU it runs on holds until the process ends.
  * - Streams: `stream` is a hipStream_t (NULL = the default stream).  Every call
  *   only enqueues work and returns, except those that hand results to the
  *   host and therefore synchronise `stream`: dgr_voxelize_plan, dgr_densify,
@@ -152,6 +154,25 @@ dgr_status dgr_voxelize_backward(const float *mu, const float *scale, const floa
                                  const dgr_trunc *trunc, const float *dvolume, float *dmu,
                                  float *dscale, float *dquat, float *ddensity, void *ws,
                                  size_t ws_bytes, void *stream);
+
+/* dgr_voxelize_backward without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  Same arguments, kernels and results as
+ * dgr_voxelize_backward (bit for bit); the 64-byte per-Gaussian records go to
+ * a fixed device array of dgr_voxelize_backward_noalloc_max() = 524,288
+ * Gaussians (above the 500K cap of the density control, Alg. 2), 32 MiB per
+ * GPU, kept until the process ends.  Nothing in it needs initial contents: a
+ * call overwrites the first n records before reading them.  n beyond the
+ * maximum returns DGR_ERR_INVALID_ARG and launches nothing.  The call itself
+ * allocates nothing; its first call on a device looks up that device's array
+ * address (the device current at the call must be the stream's).  Every call on
+ * one GPU shares the array: calls that overlap in time on one GPU (different
+ * streams, or host threads) race and give wrong gradients. */
+int64_t dgr_voxelize_backward_noalloc_max(void);
+dgr_status dgr_voxelize_backward_noalloc(const float *mu, const float *scale, const float *quat,
+                                         const float *density, int64_t n, const dgr_grid *grid,
+                                         const dgr_trunc *trunc, const float *dvolume, float *dmu,
+                                         float *dscale, float *dquat, float *ddensity, void *stream);
 
 /* ---- projection (sec. 4.3, P_hat = T(V)) and its adjoint --------------- */
 

@@ -13,6 +13,8 @@
 // reads of dL/dV are row-coalesced), accumulate the ten moments in registers,
 // reduce them across the wavefront with shuffles, and lane 0 applies the chain
 // rule in binary64.  No atomics; the result is deterministic.
+#include <mutex>
+
 #include "internal.h"
 
 namespace dgr {
@@ -152,6 +154,62 @@ __global__ __launch_bounds__(256) void voxelize_grad(
 }
 
 }  // namespace
+
+// Fixed device array holding the per-Gaussian records of the allocation-free
+// entry point.  Host code never passes its name to a kernel (in host code it
+// names a host-side stand-in): the device address comes from
+// hipGetSymbolAddress, once per device, and is kept in static_rec_ptr.
+constexpr int64_t kStaticGaussians = int64_t(1) << 19;  // 524,288 records, 32 MiB
+static __device__ __align__(256) GaussRec scratch[kStaticGaussians];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+GaussRec *g_static_rec[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call per device, with that device current).
+dgr_status static_rec_ptr(GaussRec **out) {
+    int dev = -1;
+    DGR_TRY_HIP(hipGetDevice(&dev));
+    DGR_CHECK(dev >= 0 && dev < kMaxDevices, "device %d beyond the %d supported", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (g_static_rec[dev] == nullptr) {
+        void *p = nullptr;
+        DGR_TRY_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        DGR_CHECK(p != nullptr, "no device address for the fixed record array");
+        g_static_rec[dev] = static_cast<GaussRec *>(p);
+    }
+    *out = g_static_rec[dev];
+    return DGR_OK;
+}
+
+dgr_status check_backward_args(const float *mu, const float *scale, const float *quat, const float *density,
+                               int64_t n, const dgr_grid *grid, const dgr_trunc *trunc, const float *dvolume,
+                               float *dmu, float *dscale, float *dquat, float *ddensity) {
+    dgr_status s;
+    if ((s = check_grid(grid)) != DGR_OK) return s;
+    if ((s = check_trunc(trunc)) != DGR_OK) return s;
+    DGR_CHECK(n >= 0 && n < (int64_t(1) << 31), "n = %lld out of range", (long long)n);
+    if (n == 0) return DGR_OK;
+    DGR_CHECK(mu && scale && quat && density && dvolume, "null input pointer");
+    DGR_CHECK(dmu && dscale && dquat && ddensity, "null output pointer");
+    return DGR_OK;
+}
+
+dgr_status launch_backward(const float *mu, const float *scale, const float *quat, const float *density,
+                           int64_t n, const dgr_grid *grid, const dgr_trunc *trunc, const float *dvolume,
+                           float *dmu, float *dscale, float *dquat, float *ddensity, GaussRec *rec,
+                           hipStream_t st) {
+    dgr_status s;
+    if ((s = launch_prep(mu, scale, quat, density, n, grid, trunc, rec, nullptr, nullptr, st)) != DGR_OK)
+        return s;
+    voxelize_grad<<<dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st>>>(
+        rec, n, dvolume, dev_grid(grid), scale, quat, dmu, dscale, dquat, ddensity);
+    DGR_LAUNCH_CHECK();
+    return DGR_OK;
+}
+}  // namespace
 }  // namespace dgr
 
 using namespace dgr;
@@ -166,25 +224,34 @@ extern "C" dgr_status dgr_voxelize_backward(const float *mu, const float *scale,
                                             const dgr_trunc *trunc, const float *dvolume, float *dmu,
                                             float *dscale, float *dquat, float *ddensity, void *ws,
                                             size_t ws_bytes, void *stream) {
-    dgr_status s;
-    if ((s = check_grid(grid)) != DGR_OK) return s;
-    if ((s = check_trunc(trunc)) != DGR_OK) return s;
-    DGR_CHECK(n >= 0 && n < (int64_t(1) << 31), "n = %lld out of range", (long long)n);
-    if (n == 0) return DGR_OK;
-    DGR_CHECK(mu && scale && quat && density && dvolume, "null input pointer");
-    DGR_CHECK(dmu && dscale && dquat && ddensity, "null output pointer");
+    dgr_status s = check_backward_args(mu, scale, quat, density, n, grid, trunc, dvolume, dmu, dscale, dquat,
+                                       ddensity);
+    if (s != DGR_OK || n == 0) return s;
     DGR_CHECK(ws != nullptr, "workspace is null");
     if (reinterpret_cast<uintptr_t>(ws) % kAlign)
         return fail(DGR_ERR_WORKSPACE, "workspace must be 256-byte aligned");
     if (ws_bytes < dgr_voxelize_backward_workspace(n))
         return fail(DGR_ERR_WORKSPACE, "workspace holds %zu bytes, backward needs %zu", ws_bytes,
                     dgr_voxelize_backward_workspace(n));
-    hipStream_t st = as_stream(stream);
-    GaussRec *rec = static_cast<GaussRec *>(ws);
-    if ((s = launch_prep(mu, scale, quat, density, n, grid, trunc, rec, nullptr, nullptr, st)) != DGR_OK)
-        return s;
-    voxelize_grad<<<dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st>>>(
-        rec, n, dvolume, dev_grid(grid), scale, quat, dmu, dscale, dquat, ddensity);
-    DGR_LAUNCH_CHECK();
-    return DGR_OK;
+    return launch_backward(mu, scale, quat, density, n, grid, trunc, dvolume, dmu, dscale, dquat, ddensity,
+                           static_cast<GaussRec *>(ws), as_stream(stream));
+}
+
+extern "C" int64_t dgr_voxelize_backward_noalloc_max(void) { return kStaticGaussians; }
+
+extern "C" dgr_status dgr_voxelize_backward_noalloc(const float *mu, const float *scale, const float *quat,
+                                                    const float *density, int64_t n, const dgr_grid *grid,
+                                                    const dgr_trunc *trunc, const float *dvolume, float *dmu,
+                                                    float *dscale, float *dquat, float *ddensity,
+                                                    void *stream) {
+    dgr_status s = check_backward_args(mu, scale, quat, density, n, grid, trunc, dvolume, dmu, dscale, dquat,
+                                       ddensity);
+    if (s != DGR_OK || n == 0) return s;
+    DGR_CHECK(n <= kStaticGaussians,
+              "n = %lld exceeds the %lld Gaussians the allocation-free backward holds",
+              (long long)n, (long long)kStaticGaussians);
+    GaussRec *rec = nullptr;
+    if ((s = static_rec_ptr(&rec)) != DGR_OK) return s;
+    return launch_backward(mu, scale, quat, density, n, grid, trunc, dvolume, dmu, dscale, dquat, ddensity,
+                           rec, as_stream(stream));
 }

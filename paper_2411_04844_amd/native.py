@@ -59,6 +59,9 @@ _SIGS = {
     "dgr_voxelize_backward_workspace": (ctypes.c_size_t, ["i64"]),
     "dgr_voxelize_backward": ("st", ["p", "p", "p", "p", "i64", "grid", "trunc", "p", "p", "p",
                                      "p", "p", "p", "sz", "p"]),
+    "dgr_voxelize_backward_noalloc_max": (ctypes.c_int64, []),
+    "dgr_voxelize_backward_noalloc": ("st", ["p", "p", "p", "p", "i64", "grid", "trunc", "p", "p", "p",
+                                             "p", "p", "p"]),
     "dgr_project_workspace": (ctypes.c_size_t, ["grid", "geom"]),
     "dgr_project": ("st", ["p", "grid", "geom", "p", "p", "sz", "p"]),
     "dgr_project_l1": ("st", ["p", "grid", "geom", "p", "p", "p", "p", "sz", "p"]),
@@ -247,6 +250,22 @@ def dgr_voxelize_backward(mu, scale, quat, density, dvolume, grid: GridSpec, k_s
     _check("dgr_voxelize_backward", lib().dgr_voxelize_backward(
         _ptr(mu), _ptr(scale), _ptr(quat), _ptr(density), n, ctypes.byref(g), ctypes.byref(t),
         _ptr(dvolume), *(_ptr(o) for o in outs), p, sz, _stream()))
+    return outs
+
+
+def dgr_voxelize_backward_noalloc(mu, scale, quat, density, dvolume, grid: GridSpec, k_sigma=3.0,
+                                  box_half=8, outs=None):
+    """dgr_voxelize_backward with the per-Gaussian records in the library's
+    fixed device array (no workspace)."""
+    n = mu.shape[0]
+    _need(dvolume, torch.float32, grid.shape, "dvolume")
+    if outs is None:
+        outs = (torch.empty_like(mu), torch.empty_like(scale), torch.empty_like(quat),
+                torch.empty_like(density))
+    g, t = c_grid(grid), c_trunc(k_sigma, box_half)
+    _check("dgr_voxelize_backward_noalloc", lib().dgr_voxelize_backward_noalloc(
+        _ptr(mu), _ptr(scale), _ptr(quat), _ptr(density), n, ctypes.byref(g), ctypes.byref(t),
+        _ptr(dvolume), *(_ptr(o) for o in outs), _stream()))
     return outs
 
 
