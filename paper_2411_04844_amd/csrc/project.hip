@@ -522,23 +522,47 @@ __global__ __launch_bounds__(256) void zero_u32(unsigned *__restrict__ p) { *p =
 
 __global__ __launch_bounds__(256) void absmax_bits(const float *__restrict__ x, int64_t n,
                                                    unsigned *__restrict__ out) {
+    // 16-byte loads (four in flight per thread) over the aligned body, then
+    // the ragged head and tail; one atomic per wave
     float m = 0.0f;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-        m = fmaxf(m, fabsf(x[i]));
+    const int64_t head = std::min<int64_t>(n, (int64_t)((16 - (reinterpret_cast<uintptr_t>(x) & 15)) & 15) / 4);
+    const int64_t nv = (n - head) / 4;
+    const float4 *xv = reinterpret_cast<const float4 *>(x + head);
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    for (; i + 3 * stride < nv; i += 4 * stride) {
+        float4 a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] = xv[i + u * stride];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            m = fmaxf(m, fmaxf(fmaxf(fabsf(a[u].x), fabsf(a[u].y)), fmaxf(fabsf(a[u].z), fabsf(a[u].w))));
+    }
+    for (; i < nv; i += stride) {
+        const float4 a = xv[i];
+        m = fmaxf(m, fmaxf(fmaxf(fabsf(a.x), fabsf(a.y)), fmaxf(fabsf(a.z), fabsf(a.w))));
+    }
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t < head) m = fmaxf(m, fabsf(x[t]));
+    const int64_t tail = head + 4 * nv + t;
+    if (tail < n) m = fmaxf(m, fabsf(x[tail]));
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
     if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
 }
 
-// Fixed-point scale: the largest power of two S with
+// Fixed-point scale, in binary64: the largest power of two S with
 // |proj| * |scale| * S * 2^headroom < 2^30, so that a sum of up to 2^headroom
-// weighted values still converts to a 32-bit integer.
-__device__ __forceinline__ float fixed_scale(const unsigned *maxbits, float scale, int headroom) {
+// weighted values still converts to a 32-bit integer.  S ranges over
+// 2^-128 ... 2^(180 - headroom), beyond binary32, so it is kept in binary64
+// and a value is scaled as (double)proj * (scale * S), one rounding to
+// binary32 (exact products: a binary32 times a binary32 times a power of two).
+__device__ __forceinline__ double fixed_scale(const unsigned *maxbits, float scale, int headroom) {
     const float mc = __uint_as_float(*maxbits) * fabsf(scale);
-    if (!(mc > 0.0f) || !(mc < 3.0e38f)) return 1.0f;
+    if (!(mc > 0.0f) || !(mc < 3.0e38f)) return 1.0;
     int e;
     frexpf(mc, &e);  // mc < 2^e
-    return ldexpf(1.0f, 30 - e - headroom);
+    return ldexp(1.0, 30 - e - headroom);
 }
 
 // ---- brick backprojection ---------------------------------------------------
@@ -728,7 +752,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     // the run's ends are found by testing the fixed-point cells.
     const double blo[3] = {c0x - (double)eps, c0y - (double)eps, c0z - (double)eps};
     const double bhi[3] = {c0x + kBX + (double)eps, c0y + kBY + (double)eps, c0z + kBZ + (double)eps};
-    const float gs = G.scale * fixed_scale(maxbits, G.scale, headroom);  // |proj * gs| < 2^(30 - headroom)
+    const double gs = (double)G.scale * fixed_scale(maxbits, G.scale, headroom);  // |proj * gs| < 2^(30 - headroom)
     for (int e = t; e < kBT3; e += 256) tile[e] = 0ull;
     if (t == 0) {
         q_rays = 0;
@@ -755,7 +779,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
         Ray r;
         int k0, k1;
         ray_geom(G, g, j, iu, iv, r);
-        const float gr = gs * pv;
+        const float gr = (float)(gs * (double)pv);
         // an axis without advance keeps one fixed-point cell for every
         // sample: test it once (the interval search cannot bound it)
         const bool still_ok =
@@ -871,7 +895,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
 __global__ __launch_bounds__(256) void gather_bricks(const long long *__restrict__ staging, DevGrid g,
                                                      Bricks bk, const unsigned *__restrict__ maxbits,
                                                      float scale, int headroom, float *__restrict__ V) {
-    const double inv_s = 1.0 / (double)fixed_scale(maxbits, scale, headroom);
+    const double inv_s = 1.0 / fixed_scale(maxbits, scale, headroom);
     const int64_t total = (int64_t)g.nx * g.ny * g.nz;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
         const int64_t z = i / ((int64_t)g.nx * g.ny), rem = i - z * (int64_t)g.nx * g.ny;
@@ -1064,7 +1088,7 @@ extern "C" dgr_status dgr_backproject(const float *proj, const dgr_grid *grid,
     const int64_t nproj = (int64_t)geom->n_views * geom->nu * geom->nv;
     zero_u32<<<1, 1, 0, st>>>(w.maxbits);
     DGR_LAUNCH_CHECK();
-    absmax_bits<<<dim3((unsigned)std::min<int64_t>((nproj + 255) / 256, 4096)), dim3(256), 0, st>>>(
+    absmax_bits<<<dim3((unsigned)std::min<int64_t>((nproj / 4 + 255) / 256 + 1, 2048)), dim3(256), 0, st>>>(
         proj, nproj, w.maxbits);
     DGR_LAUNCH_CHECK();
     backproject_bricks<<<dim3((unsigned)bk.count()), dim3(256), 0, st>>>(proj, g, G, bk, w.rect, eps,

@@ -264,6 +264,26 @@ def test_backproject_brick_rectangle_beyond_2_22_candidates():
     assert err < TOL and worst < 1e-5
 
 
+def test_backproject_tiny_and_huge_values():
+    """The fixed-point scale is a power of two chosen from max |g| and ranges
+    beyond binary32 (2^-128 ... 2^180): data scaled by 2^-120 or 2^100
+    backprojects to the same numbers scaled alike, and matches the oracle."""
+    grid, geom = _geoms()["cone"]
+    say("backproject tiny and huge values")
+    g = np.random.default_rng(96).normal(size=(geom.n_views, geom.nv, geom.nu)).astype(np.float32)
+    views = dev(geom.views)
+    base = native.dgr_backproject(dev(g), grid, geom, views).cpu().numpy().astype(np.float64)
+    for e in (-120, 100):
+        gs = (g.astype(np.float64) * 2.0 ** e).astype(np.float32)
+        got = native.dgr_backproject(dev(gs), grid, geom, views).cpu().numpy().astype(np.float64)
+        want = oracle.backproject(gs.astype(np.float64), grid.dims, grid.lo, grid.inv_h, geom.kind, geom.views,
+                                  geom.nu, geom.nv, geom.step, geom.length_scale)
+        say("backproject scaled 2^%d" % e, "rel_l2", rel_l2(got, want))
+        assert np.all(np.isfinite(got)) and np.abs(got).max() > 0
+        assert rel_l2(got, want) < TOL
+        assert rel_l2(got * 2.0 ** -e, base) < 1e-6
+
+
 def test_project_rays_with_disjoint_sample_ranges():
     """Two rays of one pixel bundle whose sample ranges are far apart
     ([-149, -50] and [50, 149]): the chunks between them hold no sample of
