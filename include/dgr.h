@@ -441,11 +441,11 @@ dgr_status dgr_voxelize_f64(const float *mu, const float *scale, const float *qu
  * truncation box; only rays crossing it change, so the kernel sums, over
  * those rays, |res + A dV| - |res| with res = A V - target computed in
  * binary64 from `volume` (dgr_voxelize_f64) and dV the binary64 change of the
- * Gaussian on its box for +h and -h.  out [n_jobs][n_views][2] (DEVICE,
- * binary64): per-view sums for +h and -h; the loss changes are their sums
- * over views divided by M = n_views*nu*nv.  job_gid, job_comp, job_h are HOST
- * arrays.  box_cap bounds the voxels of any job's box (larger boxes give NaN).
- * Synchronises `stream`. */
+ * Gaussian on its box for +h and -h.  out [n_jobs][2] (DEVICE, binary64):
+ * the loss changes L(+h) - L and L(-h) - L, each the sum over views (in view
+ * order) of the per-view sums, divided by M = n_views*nu*nv.  job_gid,
+ * job_comp, job_h are HOST arrays.  box_cap bounds the voxels of any job's
+ * box (larger boxes give NaN).  Synchronises `stream`. */
 size_t dgr_fd_l1_f64_workspace(int64_t n, int32_t n_jobs, int64_t box_cap, const dgr_geometry *geom);
 dgr_status dgr_fd_l1_f64(const double *volume, const dgr_grid *grid, const dgr_geometry *geom,
                          const float *target, const float *mu, const float *scale, const float *quat,

@@ -297,6 +297,18 @@ __global__ __launch_bounds__(256) void fd_rays(const double *__restrict__ V, Dev
     }
 }
 
+// Loss changes of each job: the per-view sums added in view order in
+// binary64 and divided by M (one thread per job and sign).
+__global__ __launch_bounds__(256) void fd_sum_views(const double *__restrict__ per_view, int n_jobs, int n_views,
+                                                    double inv_m, double *__restrict__ out) {
+    const int i = blockIdx.x * 256 + threadIdx.x;  // job * 2 + sign
+    if (i >= 2 * n_jobs) return;
+    const int jb = i >> 1, sg = i & 1;
+    double acc = 0.0;
+    for (int j = 0; j < n_views; ++j) acc += per_view[((int64_t)jb * n_views + j) * 2 + sg];
+    out[i] = acc * inv_m;
+}
+
 }  // namespace
 }  // namespace dgr
 
@@ -338,6 +350,7 @@ extern "C" size_t dgr_fd_l1_f64_workspace(int64_t n, int32_t n_jobs, int64_t box
     c.take<int32_t>(6 * std::max<int64_t>(n, 1));
     c.take<FdJob>(std::max(n_jobs, 1));
     c.take<double>((int64_t)std::max(n_jobs, 1) * 2 * box_cap);
+    c.take<double>((int64_t)std::max(n_jobs, 1) * geom->n_views * 2);
     return c.off;
 }
 
@@ -365,6 +378,7 @@ extern "C" dgr_status dgr_fd_l1_f64(const double *volume, const dgr_grid *grid,
     int32_t *box = c.take<int32_t>(6 * n);
     FdJob *jobs = c.take<FdJob>(n_jobs);
     double *dvol = c.take<double>((int64_t)n_jobs * 2 * box_cap);
+    double *per_view = c.take<double>((int64_t)n_jobs * geom->n_views * 2);
     if ((s = launch_prep(mu, scale, quat, nullptr, n, grid, trunc, nullptr, nullptr, box, st)) != DGR_OK)
         return s;
     // the job table (host arrays) is packed and copied to the workspace
@@ -380,7 +394,12 @@ extern "C" dgr_status dgr_fd_l1_f64(const double *volume, const dgr_grid *grid,
     DGR_LAUNCH_CHECK();
     Geom64 G{geom->kind, geom->n_views, geom->nu, geom->nv, geom->views, (double)geom->step,
              (double)geom->length_scale * (double)geom->step};
-    fd_rays<<<dim3(geom->n_views, n_jobs), dim3(256), 0, st>>>(volume, g, G, target, box, jobs, dvol, box_cap, out);
+    fd_rays<<<dim3(geom->n_views, n_jobs), dim3(256), 0, st>>>(volume, g, G, target, box, jobs, dvol, box_cap,
+                                                               per_view);
+    DGR_LAUNCH_CHECK();
+    const double m = (double)geom->n_views * geom->nu * geom->nv;
+    fd_sum_views<<<dim3((unsigned)((2 * n_jobs + 255) / 256)), dim3(256), 0, st>>>(per_view, n_jobs, geom->n_views,
+                                                                                 1.0 / m, out);
     DGR_LAUNCH_CHECK();
     DGR_TRY_HIP(hipStreamSynchronize(st));  // the host job table goes out of scope
     return DGR_OK;

@@ -181,42 +181,6 @@ __device__ bool k_interval(const Ray &r, const double lo[3], const double hi[3],
     return true;
 }
 
-// A superset of the samples with lo <= u_a <= hi, from binary32 reciprocals;
-// callers test the end samples exactly.  The binary32 sample parameter t has a
-// relative error below 5 * 2^-24 (offset and advance rounded to binary32, the
-// hardware reciprocal within one ulp, the product rounded); the interval is
-// widened by four times that plus 2^-10.  An axis with no advance only gets a
-// loose band test here: callers test such an axis exactly in fixed point.
-__device__ bool k_interval_coarse(const Ray &r, const double lo[3], const double hi[3], int *k0,
-                                  int *k1) {
-    float tmin = -3.0e38f, tmax = 3.0e38f;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const float du = (float)r.du[a];
-        // offsets from the anchor in binary64, then rounded: t keeps ~2e-7
-        // relative accuracy however large the offsets are
-        const float o0 = (float)(lo[a] - r.cu[a]), o1 = (float)(hi[a] - r.cu[a]);
-        if (du == 0.0f) {
-            if (!(o0 <= 1.0f && o1 >= -1.0f)) return false;
-            continue;
-        }
-        const float inv = __builtin_amdgcn_rcpf(du);
-        const float t0 = o0 * inv, t1 = o1 * inv;
-        tmin = fmaxf(tmin, fminf(t0, t1));
-        tmax = fminf(tmax, fmaxf(t0, t1));
-    }
-    const float slack = 0x1p-10f + 1.2e-6f * fmaxf(fabsf(tmin), fabsf(tmax));
-    tmin -= slack;
-    tmax += slack;
-    if (!(tmin <= tmax) || tmin < -(float)kMaxK || tmax > (float)kMaxK) return false;
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-        if (!(fabs(r.cu[a]) < 1073741824.0)) return false;
-    *k0 = (int)ceilf(tmin);
-    *k1 = (int)floorf(tmax);
-    return *k0 <= *k1;
-}
-
 __device__ __forceinline__ bool support_range(const Ray &r, const DevGrid &g, int *k0, int *k1) {
     // support of the interpolant: -1 <= u <= dims  (padded: 1 .. dims + 2)
     const double lo[3] = {kPad - 1.0, kPad - 1.0, kPad - 1.0};
@@ -565,6 +529,88 @@ __device__ __forceinline__ double fixed_scale(const unsigned *maxbits, float sca
     return ldexp(1.0, 30 - e - headroom);
 }
 
+// ---- per-ray table of the backprojection -------------------------------------
+// Every ray is set up once per view batch (binary64 geometry, fixed-point
+// anchor and advance, the scaled projection value) and read by each brick its
+// shadow rectangle holds, instead of once per brick (a ray crosses about 20
+// bricks of the 256^3 workload).  48 bytes per ray, 16-byte aligned.
+struct alignas(16) RayTab {
+    long long U[3];   // anchor, padded voxel coordinates, 32.32 fixed point
+    unsigned dlo[3];  // low words of the advance per sample
+    unsigned meta;    // [0, 9): high words of the advance, 3-bit two's complement per axis;
+                      // bit 31: no sample of the ray lies in the support, or g = 0
+    float gr;         // projection value times length_scale * step * the fixed-point scale
+    unsigned pad;
+};
+static_assert(sizeof(RayTab) == 48, "ray table rows are 48 bytes");
+constexpr unsigned kRayMiss = 0x80000000u;
+// Table budget per batch of views (bytes); larger scans are backprojected in
+// several batches that add into the same integer tiles.
+constexpr int64_t kRayTableBudget = int64_t(4) << 30;
+
+__global__ __launch_bounds__(256) void ray_table(const float *__restrict__ proj, GeomDev G, DevGrid g,
+                                                 int j0, int64_t nrays, const unsigned *__restrict__ maxbits,
+                                                 int headroom, RayTab *__restrict__ tab);
+
+// One thread per ray of views j0 ... (nrays rays in all).
+__global__ __launch_bounds__(256) void ray_table(const float *__restrict__ proj, GeomDev G, DevGrid g,
+                                                 int j0, int64_t nrays, const unsigned *__restrict__ maxbits,
+                                                 int headroom, RayTab *__restrict__ tab) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= nrays) return;
+    const int64_t per_view = (int64_t)G.nu * G.nv;
+    const int jl = (int)(i / per_view);
+    const int64_t pix = i - (int64_t)jl * per_view;
+    const int iv = (int)(pix / G.nu), iu = (int)(pix - (int64_t)iv * G.nu);
+    const int j = j0 + jl;
+    const double gs = (double)G.scale * fixed_scale(maxbits, G.scale, headroom);
+    const float gr = (float)(gs * (double)proj[(int64_t)j * per_view + pix]);
+    Ray r;
+    ray_geom(G, g, j, iu, iv, r);
+    int k0, k1;
+    // a ray with no sample in the support (or beyond the fixed-point limits of
+    // support_range) is a miss for the projector, and so for its transpose
+    const bool hit = gr != 0.0f && support_range(r, g, &k0, &k1);
+    RayTab t;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        t.U[a] = r.U[a];
+        t.dlo[a] = (unsigned)r.DU[a];
+    }
+    t.meta = (((unsigned)(r.DU[0] >> 32) & 7u)) | (((unsigned)(r.DU[1] >> 32) & 7u) << 3) |
+             (((unsigned)(r.DU[2] >> 32) & 7u) << 6) | (hit ? 0u : kRayMiss);
+    t.gr = gr;
+    t.pad = 0u;
+    tab[i] = t;
+}
+
+// Samples k whose fixed-point position lies in [lo, hi] on every axis with an
+// advance, from binary32 estimates: a superset, whose ends the caller tests
+// exactly.  t = (lo - U) / DU: both integers rounded to binary32 (through
+// binary64, total error below 2^-24 each), the hardware reciprocal within one
+// ulp and the product rounded keep the relative error of t below 5 * 2^-24;
+// the interval is widened by four times that plus 2^-10.  Axes without
+// advance are left to the caller.
+__device__ bool k_interval_fixed(const long long U[3], const long long DU[3], const long long lo[3],
+                                 const long long hi[3], int *k0, int *k1) {
+    float tmin = -3.0e38f, tmax = 3.0e38f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (DU[a] == 0) continue;
+        const float inv = __builtin_amdgcn_rcpf((float)(double)DU[a]);
+        const float t0 = (float)(double)(lo[a] - U[a]) * inv, t1 = (float)(double)(hi[a] - U[a]) * inv;
+        tmin = fmaxf(tmin, fminf(t0, t1));
+        tmax = fminf(tmax, fmaxf(t0, t1));
+    }
+    const float slack = 0x1p-10f + 1.2e-6f * fmaxf(fabsf(tmin), fabsf(tmax));
+    tmin -= slack;
+    tmax += slack;
+    if (!(tmin <= tmax) || tmin < -(float)kMaxK || tmax > (float)kMaxK) return false;
+    *k0 = (int)ceilf(tmin);
+    *k1 = (int)floorf(tmax);
+    return *k0 <= *k1;
+}
+
 // ---- brick backprojection ---------------------------------------------------
 // One work-group per brick, two phases repeated until every view is done.
 //  1. Ray set-up: each thread takes one candidate pixel of a view's shadow
@@ -728,12 +774,9 @@ __device__ __forceinline__ void march_segments(unsigned long long *tile, const R
 // in a brick has more than kMaxSeg segments (and no more than 256 samples).
 // Three work-groups per CU (51 KB of LDS each, <= 168 VGPRs): the extra waves
 // overlap one work-group's LDS adds with another's arithmetic.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void backproject_bricks(const float *__restrict__ proj, DevGrid g,
-                                                          GeomDev G, Bricks bk,
-                                                          const ushort4 *__restrict__ rect,
-                                                          float eps, const unsigned *__restrict__ maxbits,
-                                                          int seg_shift, int headroom,
-                                                          long long *__restrict__ staging) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void backproject_bricks(
+    const RayTab *__restrict__ tab, int j0, int nj, GeomDev G, Bricks bk, const ushort4 *__restrict__ rect,
+    int seg_shift, int accumulate, long long *__restrict__ staging) {
     __shared__ unsigned long long tile[kBT3];
     __shared__ RayRec rays[kRayCap];
     __shared__ unsigned short segs[kSegCap];
@@ -745,22 +788,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     // brick cells in padded coordinates: [c0, c0 + kB)
     const int c0x = bx * kBX - 1 + kPad, c0y = by * kBY - 1 + kPad, c0z = bz * kBZ - 1 + kPad;
     const long long C0x = (long long)c0x << 32, C0y = (long long)c0y << 32, C0z = (long long)c0z << 32;
-    // The candidate k-range is exact in binary64 for the brick grown by eps, a
-    // bound on |fixed-point position - binary64 position|, so it holds every
-    // sample whose fixed-point cell is in the brick.  Those samples form one
-    // run of k (each axis test is an interval of the exact integer positions);
-    // the run's ends are found by testing the fixed-point cells.
-    const double blo[3] = {c0x - (double)eps, c0y - (double)eps, c0z - (double)eps};
-    const double bhi[3] = {c0x + kBX + (double)eps, c0y + kBY + (double)eps, c0z + kBZ + (double)eps};
-    const double gs = (double)G.scale * fixed_scale(maxbits, G.scale, headroom);  // |proj * gs| < 2^(30 - headroom)
-    for (int e = t; e < kBT3; e += 256) tile[e] = 0ull;
+    // Bounds of the candidate k-range: the brick's cells in fixed point (a
+    // sample is in the brick iff its fixed-point cell is); the range from the
+    // binary32 estimate is a superset of the samples in the brick, which form
+    // one run of k (each axis test is an interval of the exact integer
+    // positions), and the run's ends are found by testing the cells.
+    const long long blo[3] = {C0x, C0y, C0z};
+    const long long bhi[3] = {C0x + ((long long)kBX << 32), C0y + ((long long)kBY << 32),
+                              C0z + ((long long)kBZ << 32)};
+    const int64_t per_view = (int64_t)G.nu * G.nv;
+    long long *out = staging + b * kBT3;
+    for (int e = t; e < kBT3; e += 256) tile[e] = accumulate ? (unsigned long long)out[e] : 0ull;
     if (t == 0) {
         q_rays = 0;
         q_segs = 0;
     }
     __syncthreads();
-    // Ray set-up (phase 1) of candidate c of view j's rectangle rc: the
-    // record and the number of the ray's samples in the brick (0: none).
+    // Ray set-up (phase 1) of candidate c of view j's rectangle rc, from the
+    // ray's table row: the record and the number of the ray's samples in the
+    // brick (0: none).
     auto setup = [&](int j, const ushort4 &rc, float inu, long long c, RayRec &rec) -> int {
         const int nu_r = (int)rc.y - (int)rc.x + 1;
         int n = 0;
@@ -775,53 +821,51 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
             col = (int)(c - (long long)row * nu_r);
         }
         const int iv = (int)rc.z + row, iu = (int)rc.x + col;
-        const float pv = proj[((int64_t)j * G.nv + iv) * G.nu + iu];
-        Ray r;
-        int k0, k1;
-        ray_geom(G, g, j, iu, iv, r);
-        const float gr = (float)(gs * (double)pv);
+        const RayTab rt = tab[(int64_t)(j - j0) * per_view + (int64_t)iv * G.nu + iu];
+        if (rt.meta & kRayMiss) return 0;
+        long long DU[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            DU[a] = (long long)(((unsigned long long)(long long)((int)(rt.meta << (29 - 3 * a)) >> 29) << 32) |
+                                rt.dlo[a]);
+        const float gr = rt.gr;
         // an axis without advance keeps one fixed-point cell for every
-        // sample: test it once (the interval search cannot bound it)
+        // sample: test it once (the interval estimate cannot bound it)
         const bool still_ok =
-            (r.DU[0] != 0 || (unsigned long long)(r.U[0] - C0x) < ((unsigned long long)kBX << 32)) &&
-            (r.DU[1] != 0 || (unsigned long long)(r.U[1] - C0y) < ((unsigned long long)kBY << 32)) &&
-            (r.DU[2] != 0 || (unsigned long long)(r.U[2] - C0z) < ((unsigned long long)kBZ << 32));
-        if (gr != 0.0f && still_ok) {
-            if (k_interval_coarse(r, blo, bhi, &k0, &k1)) {
-                long long ux = r.U[0] + (long long)k0 * r.DU[0] - C0x;
-                long long uy = r.U[1] + (long long)k0 * r.DU[1] - C0y;
-                long long uz = r.U[2] + (long long)k0 * r.DU[2] - C0z;
-                while (k0 <= k1 && !in_brick(ux, uy, uz)) {
-                    ++k0;
-                    ux += r.DU[0];
-                    uy += r.DU[1];
-                    uz += r.DU[2];
+            (DU[0] != 0 || (unsigned long long)(rt.U[0] - C0x) < ((unsigned long long)kBX << 32)) &&
+            (DU[1] != 0 || (unsigned long long)(rt.U[1] - C0y) < ((unsigned long long)kBY << 32)) &&
+            (DU[2] != 0 || (unsigned long long)(rt.U[2] - C0z) < ((unsigned long long)kBZ << 32));
+        int k0, k1;
+        if (still_ok && k_interval_fixed(rt.U, DU, blo, bhi, &k0, &k1)) {
+            long long ux = rt.U[0] + (long long)k0 * DU[0] - C0x;
+            long long uy = rt.U[1] + (long long)k0 * DU[1] - C0y;
+            long long uz = rt.U[2] + (long long)k0 * DU[2] - C0z;
+            while (k0 <= k1 && !in_brick(ux, uy, uz)) {
+                ++k0;
+                ux += DU[0];
+                uy += DU[1];
+                uz += DU[2];
+            }
+            if (k0 <= k1) {
+                long long vx = rt.U[0] + (long long)k1 * DU[0] - C0x;
+                long long vy = rt.U[1] + (long long)k1 * DU[1] - C0y;
+                long long vz = rt.U[2] + (long long)k1 * DU[2] - C0z;
+                while (!in_brick(vx, vy, vz)) {  // stops at k0 at the latest
+                    --k1;
+                    vx -= DU[0];
+                    vy -= DU[1];
+                    vz -= DU[2];
                 }
-                if (k0 <= k1) {
-                    long long vx = r.U[0] + (long long)k1 * r.DU[0] - C0x;
-                    long long vy = r.U[1] + (long long)k1 * r.DU[1] - C0y;
-                    long long vz = r.U[2] + (long long)k1 * r.DU[2] - C0z;
-                    while (!in_brick(vx, vy, vz)) {  // stops at k0 at the latest
-                        --k1;
-                        vx -= r.DU[0];
-                        vy -= r.DU[1];
-                        vz -= r.DU[2];
-                    }
-                    n = k1 - k0 + 1;
-                    rec.ulo[0] = (unsigned)ux;
-                    rec.ulo[1] = (unsigned)uy;
-                    rec.ulo[2] = (unsigned)uz;
-                    rec.dlo[0] = (unsigned)r.DU[0];
-                    rec.dlo[1] = (unsigned)r.DU[1];
-                    rec.dlo[2] = (unsigned)r.DU[2];
-                    rec.gr = gr;
-                    rec.meta = (unsigned)(ux >> 32) | ((unsigned)(uy >> 32) << 5) |
-                               ((unsigned)(uz >> 32) << 10) |
-                               (((unsigned)(r.DU[0] >> 32) & 7u) << 15) |
-                               (((unsigned)(r.DU[1] >> 32) & 7u) << 18) |
-                               (((unsigned)(r.DU[2] >> 32) & 7u) << 21) |
-                               ((unsigned)(n - 1) << 24);
-                }
+                n = k1 - k0 + 1;
+                rec.ulo[0] = (unsigned)ux;
+                rec.ulo[1] = (unsigned)uy;
+                rec.ulo[2] = (unsigned)uz;
+                rec.dlo[0] = rt.dlo[0];
+                rec.dlo[1] = rt.dlo[1];
+                rec.dlo[2] = rt.dlo[2];
+                rec.gr = gr;
+                rec.meta = (unsigned)(ux >> 32) | ((unsigned)(uy >> 32) << 5) | ((unsigned)(uz >> 32) << 10) |
+                           ((rt.meta & 0x1ffu) << 15) | ((unsigned)(n - 1) << 24);
             }
         }
         return n;
@@ -830,16 +874,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     // consecutive pixels of a rectangle, so the projection reads coalesce):
     // the chunk starting at candidate cb of view j.  advance() moves to the
     // next chunk, skipping empty rectangles; j == n_views when done.
-    int j = -1;
+    const int jend = j0 + nj;
+    int j = j0 - 1;
     long long cb = -kChunk, ncand = 0;  // a rectangle may hold up to 2^32 pixels
     float inu = 1.0f;  // 1 / rectangle width
-    ushort4 rc = make_ushort4(1, 0, 1, 0), rc_next = rect[b];
+    ushort4 rc = make_ushort4(1, 0, 1, 0), rc_next = rect[(int64_t)j0 * nb + b];
     auto advance = [&]() {
         cb += kChunk;
         while (cb >= ncand) {
-            if (++j >= G.n_views) return;
+            if (++j >= jend) return;
             rc = rc_next;
-            if (j + 1 < G.n_views) rc_next = rect[(int64_t)(j + 1) * nb + b];  // prefetch
+            if (j + 1 < jend) rc_next = rect[(int64_t)(j + 1) * nb + b];  // prefetch
             const int nu_r = (int)rc.y - (int)rc.x + 1, nv_r = (int)rc.w - (int)rc.z + 1;
             ncand = (nu_r > 0 && nv_r > 0) ? (long long)nu_r * nv_r : 0;
             inu = nu_r > 0 ? 1.0f / (float)nu_r : 1.0f;
@@ -849,8 +894,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     RayRec rec;
     int n = 0;
     advance();
-    if (j < G.n_views && cb + t < ncand) n = setup(j, rc, inu, cb + t, rec);
-    while (j < G.n_views) {
+    if (j < jend && cb + t < ncand) n = setup(j, rc, inu, cb + t, rec);
+    while (j < jend) {
         // ---- queue the chunk's rays and segments (the queue is empty)
         const int nseg = (n + (1 << seg_shift) - 1) >> seg_shift;
         const unsigned long long mask = __ballot(n > 0);
@@ -877,7 +922,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
         march_segments(tile, rays, segs, ns, seg_shift);
         advance();
         n = 0;
-        if (j < G.n_views && cb + t < ncand) n = setup(j, rc, inu, cb + t, rec);
+        if (j < jend && cb + t < ncand) n = setup(j, rc, inu, cb + t, rec);
         __syncthreads();
         if (t == 0) {
             q_rays = 0;
@@ -885,7 +930,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
         }
         __syncthreads();
     }
-    long long *out = staging + b * kBT3;
     for (int e = t; e < kBT3; e += 256) out[e] = (long long)tile[e];
 }
 
@@ -932,6 +976,8 @@ struct ProjWs {
     long long *staging;
     ushort4 *rect;
     unsigned *maxbits;
+    RayTab *tab;
+    int batch_views;  // views per backprojection batch (ray table rows: batch_views * nu * nv)
     size_t bytes;
 };
 
@@ -954,6 +1000,11 @@ ProjWs carve_proj_ws(void *ws, const dgr_grid *grid, const dgr_geometry *geom) {
     w.staging = b.take<long long>(bk.count() * kBT3);
     w.rect = b.take<ushort4>(bk.count() * geom->n_views);
     w.maxbits = b.take<unsigned>(1);
+    const int64_t row_bytes = (int64_t)geom->nu * geom->nv * (int64_t)sizeof(RayTab);
+    const int64_t fit = std::max<int64_t>(1, kRayTableBudget / std::max<int64_t>(row_bytes, 1));
+    const int64_t nbatch = (geom->n_views + fit - 1) / fit;  // equal batches
+    w.batch_views = (int)((geom->n_views + nbatch - 1) / nbatch);
+    w.tab = b.take<RayTab>((int64_t)w.batch_views * geom->nu * geom->nv);
     w.bytes = std::max(f.off, b.off);
     return w;
 }
@@ -1082,19 +1133,25 @@ extern "C" dgr_status dgr_backproject(const float *proj, const dgr_grid *grid,
     const int64_t nrect = bk.count() * geom->n_views;
     brick_rects<<<dim3((unsigned)((nrect + 255) / 256)), dim3(256), 0, st>>>(G, g, bk, w.rect);
     DGR_LAUNCH_CHECK();
-    // Fixed-point positions differ from binary64 ones by at most
-    // (|k| + 1) * 2^-33 <= 2^-10 voxel for |k| <= 2^22; grow the brick by 2^-8.
-    const float eps = 0.00390625f;
     const int64_t nproj = (int64_t)geom->n_views * geom->nu * geom->nv;
     zero_u32<<<1, 1, 0, st>>>(w.maxbits);
     DGR_LAUNCH_CHECK();
     absmax_bits<<<dim3((unsigned)std::min<int64_t>((nproj / 4 + 255) / 256 + 1, 2048)), dim3(256), 0, st>>>(
         proj, nproj, w.maxbits);
     DGR_LAUNCH_CHECK();
-    backproject_bricks<<<dim3((unsigned)bk.count()), dim3(256), 0, st>>>(proj, g, G, bk, w.rect, eps,
-                                                                         w.maxbits, seg_shift, headroom,
-                                                                         w.staging);
-    DGR_LAUNCH_CHECK();
+    // views in batches whose ray table fits the budget; each batch adds into
+    // the integer tiles of the previous ones
+    for (int j0 = 0; j0 < geom->n_views; j0 += w.batch_views) {
+        const int nj = std::min(w.batch_views, geom->n_views - j0);
+        const int64_t nrays = (int64_t)nj * geom->nu * geom->nv;
+        ray_table<<<dim3((unsigned)((nrays + 255) / 256)), dim3(256), 0, st>>>(proj, G, g, j0, nrays, w.maxbits,
+                                                                              headroom, w.tab);
+        DGR_LAUNCH_CHECK();
+        backproject_bricks<<<dim3((unsigned)bk.count()), dim3(256), 0, st>>>(w.tab, j0, nj, G, bk, w.rect,
+                                                                             seg_shift, j0 > 0 ? 1 : 0,
+                                                                             w.staging);
+        DGR_LAUNCH_CHECK();
+    }
     const int64_t nvox = (int64_t)grid->dims[0] * grid->dims[1] * grid->dims[2];
     gather_bricks<<<dim3(grid_stride_blocks(nvox)), dim3(256), 0, st>>>(w.staging, g, bk, w.maxbits,
                                                                         G.scale, headroom, volume);

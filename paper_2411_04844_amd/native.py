@@ -402,14 +402,14 @@ def dgr_voxelize_f64(mu, scale, quat, density, grid: GridSpec, k_sigma=3.0, box_
 def dgr_fd_l1_f64(volume64, target, mu, scale, quat, density, grid: GridSpec, geom: Geometry,
                   views_dev, jobs, box_cap=1 << 16, k_sigma=3.0, box_half=8):
     """jobs: list of (gid, component, h).  Returns float64 [n_jobs, 2] of loss
-    changes (L(+h) - L, L(-h) - L), summed over views and divided by M."""
+    changes (L(+h) - L, L(-h) - L)."""
     import numpy as np
     n = mu.shape[0]
     nj = len(jobs)
     gid = np.ascontiguousarray([j[0] for j in jobs], np.int32)
     comp = np.ascontiguousarray([j[1] for j in jobs], np.int32)
     hh = np.ascontiguousarray([j[2] for j in jobs], np.float64)
-    out = torch.empty((nj, geom.n_views, 2), dtype=torch.float64, device=mu.device)
+    out = torch.empty((nj, 2), dtype=torch.float64, device=mu.device)
     g, t, G = c_grid(grid), c_trunc(k_sigma, box_half), c_geom(geom, views_dev)
     ws = Workspace(mu.device)
     p, sz = ws.ptr_size(int(lib().dgr_fd_l1_f64_workspace(n, nj, int(box_cap), ctypes.byref(G))))
@@ -418,8 +418,7 @@ def dgr_fd_l1_f64(volume64, target, mu, scale, quat, density, grid: GridSpec, ge
         _ptr(quat), _ptr(density), n, ctypes.byref(t), gid.ctypes.data_as(ctypes.c_void_p),
         comp.ctypes.data_as(ctypes.c_void_p), hh.ctypes.data_as(ctypes.c_void_p), nj, int(box_cap),
         _ptr(out), p, sz, _stream()))
-    M = geom.n_views * geom.nu * geom.nv
-    return out.sum(dim=1) / M
+    return out
 
 
 def dgr_fdk(proj, grid: GridSpec, geom: Geometry, views_dev, arc=2 * 3.141592653589793, out=None,

@@ -55,17 +55,58 @@ def test_full_voxelize(full):
     assert np.array_equal(gbox, box)
 
 
+SEL = [0, 137, 271]
+_oracle_views = {}
+
+
+def _oracle_projection(full, V):
+    """The oracle's projection of three of the 360 views (computed once)."""
+    grid, geom = full[0], full[1]
+    if "P" not in _oracle_views:
+        _oracle_views["P"] = oracle.project(V.cpu().numpy().astype(np.float64), grid.dims, grid.lo, grid.inv_h,
+                                            geom.kind, geom.views[SEL], geom.nu, geom.nv, geom.step,
+                                            geom.length_scale)
+    return _oracle_views["P"]
+
+
 def test_full_project_sampled_views(full):
     grid, geom, G, d, views, box = full
     say("full project")
     V = native.dgr_voxelize(d["mu"], d["scale"], d["quat"], d["density"], grid)
     P = native.dgr_project(V, grid, geom, views).cpu().numpy()
-    sel = [0, 137, 271]
-    want = oracle.project(V.cpu().numpy().astype(np.float64), grid.dims, grid.lo, grid.inv_h,
-                          geom.kind, geom.views[sel], geom.nu, geom.nv, geom.step, geom.length_scale)
-    err = rel_l2(P[sel], want)
+    want = _oracle_projection(full, V)
+    err = rel_l2(P[SEL], want)
     say("full project rel_l2 (3 views)", err)
     assert err < TOL
+
+
+def test_full_project_l1_sampled_views(full):
+    """The fused projection + L1 launch against the bench's target (noisy
+    analytic projections of the ellipsoid phantom): dL/dP = sign(P - y) / M on
+    the three oracle views wherever the oracle's residual is settled (beyond
+    the projection's 1e-5 tolerance), and the loss against the binary64 mean
+    of |P - y| over all 360 views from the separately checked projection."""
+    grid, geom, G, d, views, box = full
+    say("full project_l1")
+    ph = inputs.ellipsoid_phantom(2002)
+    y = inputs.add_noise(inputs.phantom_projections(ph, geom, device="cuda"), 2003).contiguous()
+    V = native.dgr_voxelize(d["mu"], d["scale"], d["quat"], d["density"], grid)
+    loss, g = native.dgr_project_l1(V, y, grid, geom, views)
+    P = native.dgr_project(V, grid, geom, views)
+    M = geom.n_views * geom.nu * geom.nv
+    want_loss = float((P.double() - y.double()).abs().sum()) / M
+    say("full project_l1 loss", float(loss), "binary64 mean of the projection", want_loss)
+    assert abs(float(loss) - want_loss) <= TOL * want_loss
+    Po = _oracle_projection(full, V)
+    yo = y[SEL].cpu().numpy().astype(np.float64)
+    r = Po - yo
+    gs = g[SEL].cpu().numpy()
+    settled = np.abs(r) > TOL * np.abs(Po).max()
+    assert settled.mean() > 0.9
+    want_g = np.sign(r) / M
+    mism = int(np.count_nonzero(gs[settled].astype(np.float64) != want_g[settled].astype(np.float32)))
+    say("full project_l1 sign mismatches on settled pixels", mism, "of", int(settled.sum()))
+    assert mism == 0
 
 
 def test_full_backproject_sampled_views_and_adjoint(full):
