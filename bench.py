@@ -26,7 +26,10 @@ METRIC = "fwd+bwd ms/iter @256^3,100k Gaussians,360 views; s to 35 dB PSNR vs pl
 
 # MI355X published peaks
 HBM_PEAK_GBS = 8000.0
-FP32_VALU_PEAK_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz, no packed FP32
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # published binary32 vector peak
+# Single-issue VALU rate derived from the chip: 256 CU x 4 SIMD x 16 lanes x 2.4 GHz
+# lane-instructions per second (one wave64 instruction per SIMD every 4 cycles)
+VALU_LANE_INSTR_PER_S = 256 * 4 * 16 * 2.4e9
 
 # Algorithmic work per ray sample: position, weights, seven lerps and the sum
 # (forward); position, weights, eight products (backward)
@@ -64,40 +67,48 @@ def count_samples(prob) -> int:
 
 
 REPO = os.path.dirname(os.path.abspath(__file__))
-TRAFFIC_FILE = os.path.join(REPO, "profiles", "hbm_traffic_cone256.txt")
-KERNEL_SOURCE = {"backproject": "backproject_bricks", "project_l1": "project_bundles"}
+COUNTER_FILE = os.path.join(REPO, "profiles", "counters_cone256.txt")
+KERNEL_SOURCE = {"backproject": "backproject_bricks", "project_l1": "project_bundles<1>"}
+# the source file each profiled kernel is built from (with internal.h)
+KERNEL_FILE = {"backproject_bricks": "project.hip", "project_bundles<1>": "project.hip",
+               "voxelize_tiles": "voxelize.hip", "voxelize_grad": "voxelize_bwd.hip",
+               "ssim_fwd": "objective.hip", "ssim_bwd": "objective.hip", "tv_kernel": "objective.hip",
+               "adam_kernel": "adam.hip"}
 
 
-def source_digest(names=("project.hip", "internal.h")) -> str:
-    """sha256 of the sources the projector kernels are built from, to tell
-    whether committed counters still apply to them."""
+def source_digest(name: str) -> str:
+    """sha256 (first 16 hex) of a kernel's source file and internal.h, to tell
+    whether committed counters still apply to the kernel."""
     h = hashlib.sha256()
     cdir = os.path.join(REPO, "paper_2411_04844_amd", "csrc")
-    for name in names:
-        with open(os.path.join(cdir, name), "rb") as f:
-            h.update(name.encode() + b"\0" + f.read())
+    for fn in (name, "internal.h"):
+        with open(os.path.join(cdir, fn), "rb") as f:
+            h.update(fn.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
 
 
-def hbm_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 --pmc
-    summary (FETCH_SIZE and WRITE_SIZE, each scaled by the ratio of known
-    bytes to counter reading for a plain copy kernel), or None when the
-    summary is missing or was taken on other sources."""
-    if not os.path.exists(TRAFFIC_FILE):
+def committed_counters(kernel: str):
+    """Per-launch counters of `kernel` from the committed rocprofv3 --pmc
+    summary, with HBM bytes (FETCH_SIZE and WRITE_SIZE, each scaled by the
+    ratio of known bytes to counter reading for a plain copy kernel), or None
+    when the summary is missing or was taken on other sources."""
+    if not os.path.exists(COUNTER_FILE):
         return None
     rows = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(COUNTER_FILE):
         if line.startswith("#") or not line.strip():
             continue
         f = line.split()
         rows[f[0]] = dict(zip(f[1::2], f[2::2]))
     cal, k = rows.get("copy_calibration"), rows.get(kernel)
-    if not cal or not k or k.get("source") != source_digest():
+    if not cal or not k or k.get("source") != source_digest(KERNEL_FILE[kernel]):
         return None
     fetch_factor = float(cal["read_bytes"]) / (float(cal["fetch_kib"]) * 1024.0)
     write_factor = float(cal["write_bytes"]) / (float(cal["write_kib"]) * 1024.0)
-    return float(k["fetch_kib"]) * 1024.0 * fetch_factor + float(k["write_kib"]) * 1024.0 * write_factor
+    out = {c: float(v) for c, v in k.items() if c != "source"}
+    out["hbm_bytes"] = (float(k["fetch_kib"]) * 1024.0 * fetch_factor +
+                        float(k["write_kib"]) * 1024.0 * write_factor)
+    return out
 
 
 def copy_calibration(mib: int = 1024, reps: int = 3):
@@ -114,33 +125,39 @@ def copy_calibration(mib: int = 1024, reps: int = 3):
 
 def recon_leg(max_iters: int):
     """Sparse-view loop (256^3, 25 views, 1 % noise): time from resident
-    projections to the first PSNR >= 35 dB (checked every 10 iterations) for
-    the plain FDK-sampled initialisation (50,000 Gaussians of 1.5 voxels, the
-    loop's specification; the same with 3-voxel Gaussians; 150,000, the
-    paper's own initial count) and for the learned initialisation (50,000
-    Gaussians proposed by the U-Net); the plain ones also with the paper's
-    full objective (0.6 L1 + 0.2 SSIM + 1 TV)."""
+    projections to the first PSNR >= 35 dB for the plain FDK-sampled
+    initialisation (50,000 Gaussians of 1.5 voxels, the loop's
+    specification; the same with 3-voxel Gaussians; 150,000, the paper's own
+    initial count) and for the learned initialisation (50,000 Gaussians
+    proposed by the U-Net), with the L1 objective and with the paper's full
+    objective (0.6 L1 + 0.2 SSIM + 1 TV).  Every run is capped at max_iters
+    iterations; the PSNR is measured after every iteration, so the step that
+    first reaches 35 dB is exact."""
     from paper_2411_04844_amd import learned, recon
     prob, gt = recon.sparse_view_problem(device="cuda")
     params = learned.load() if os.path.exists(learned.WEIGHTS) else None
     out = []
     for kind, n, sv, obj in (("plain", 50_000, 1.5, "l1"), ("plain", 50_000, 3.0, "l1"),
                              ("plain", 150_000, 1.5, "l1"), ("learned", 50_000, None, "l1"),
-                             ("plain", 50_000, 1.5, "full"), ("plain", 50_000, 3.0, "full")):
+                             ("plain", 50_000, 1.5, "full"), ("plain", 50_000, 3.0, "full"),
+                             ("learned", 50_000, None, "full")):
         if kind == "learned" and params is None:
             continue
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         prob.params = (recon.fdk_init(prob, n=n, scale_vox=sv) if kind == "plain"
                        else learned.learned_init(prob, params, n=n))
-        res = recon.reconstruct(prob, gt, max_iters=max_iters, t_start=t0, objective=obj,
-                                log=lambda m: log(f"recon {kind} n={n} {obj}:", m))
+        res = recon.reconstruct(prob, gt, max_iters=max_iters, t_start=t0, objective=obj, check_every=100,
+                                log=lambda m: log(f"recon {kind} n={n} sv={sv} {obj}:", m))
+        h = res["history"]
         out.append({"init": kind, "gaussians": n, "scale_voxels": sv, "objective": obj,
                     "target_psnr_db": 35.0, "max_iters": max_iters,
                     "iterations_to_target": res["iterations"],
                     "seconds_to_target": None if res["seconds"] is None else round(res["seconds"], 3),
+                    "psnr_after_init_db": round(h[0][2], 3),
                     "best_psnr_db": round(res["best_psnr"], 3), "best_iter": res["best_iter"],
-                    "seconds_total": round(res["history"][-1][1], 2)})
+                    "final_psnr_db": round(res["final_psnr"], 3), "iterations_run": h[-1][0],
+                    "seconds_total": round(h[-1][1], 2)})
     return out
 
 
@@ -238,39 +255,82 @@ def fvr_leg(reps: int = 5):
     return out
 
 
-def cpu_baseline(prob, n_views_sample: int):
-    """Time the binary64 oracle on a bounded sample of the same workload."""
+def cpu_baseline(prob, n_views_sample: int, n_views_single: int = 2):
+    """Time the binary64 oracle on a bounded sample of the same workload, on
+    all host cores and on one."""
     import oracle
-    from paper_2411_04844_amd import inputs
     g = prob.grid
     P = {k: v.cpu().numpy() for k, v in prob.params.items()}
     nthreads = oracle.num_threads()
-    t = time.perf_counter()
-    box = oracle.bbox(P["mu"], P["scale"], P["quat"], g.dims, g.lo, g.inv_h)
-    V = oracle.voxelize(P["mu"], P["scale"], P["quat"], P["density"], g.dims, g.lo, g.inv_h, box)
-    t_vox = time.perf_counter() - t
-    sel = np.linspace(0, prob.geom.n_views - 1, n_views_sample).round().astype(int)
-    views = prob.geom.views[sel]
-    y = prob.target[sel].cpu().numpy()
-    t = time.perf_counter()
-    Ph = oracle.project(V, g.dims, g.lo, g.inv_h, prob.geom.kind, views, prob.geom.nu, prob.geom.nv,
-                        prob.geom.step, prob.geom.length_scale)
-    _, gr = oracle.l1(Ph, y)
-    t_proj = time.perf_counter() - t
-    t = time.perf_counter()
-    dV = oracle.backproject(gr, g.dims, g.lo, g.inv_h, prob.geom.kind, views, prob.geom.nu,
-                            prob.geom.nv, prob.geom.step, prob.geom.length_scale)
-    t_bp = time.perf_counter() - t
-    t = time.perf_counter()
-    oracle.voxelize_grad(P["mu"], P["scale"], P["quat"], P["density"], g.dims, g.lo, g.inv_h, box, dV)
-    t_grad = time.perf_counter() - t
-    scale = prob.geom.n_views / n_views_sample
-    ms = 1e3 * (t_vox + t_grad + (t_proj + t_bp) * scale)
-    wall = t_vox + t_proj + t_bp + t_grad
-    return {"value": round(ms, 1), "unit": "ms/iter", "cores": nthreads, "kind": "oracle",
-            "sample": (f"binary64 oracle: full voxelization and voxelization gradient "
-                       f"(100k Gaussians, 256^3), projection+L1 and backprojection over "
-                       f"{n_views_sample} of 360 views scaled x{scale:.1f}; {wall:.1f} s wall")}
+
+    def run(nv):
+        t = time.perf_counter()
+        box = oracle.bbox(P["mu"], P["scale"], P["quat"], g.dims, g.lo, g.inv_h)
+        V = oracle.voxelize(P["mu"], P["scale"], P["quat"], P["density"], g.dims, g.lo, g.inv_h, box)
+        t_vox = time.perf_counter() - t
+        sel = np.linspace(0, prob.geom.n_views - 1, nv).round().astype(int)
+        views = prob.geom.views[sel]
+        y = prob.target[sel].cpu().numpy()
+        t = time.perf_counter()
+        Ph = oracle.project(V, g.dims, g.lo, g.inv_h, prob.geom.kind, views, prob.geom.nu, prob.geom.nv,
+                            prob.geom.step, prob.geom.length_scale)
+        _, gr = oracle.l1(Ph, y)
+        t_proj = time.perf_counter() - t
+        t = time.perf_counter()
+        dV = oracle.backproject(gr, g.dims, g.lo, g.inv_h, prob.geom.kind, views, prob.geom.nu,
+                                prob.geom.nv, prob.geom.step, prob.geom.length_scale)
+        t_bp = time.perf_counter() - t
+        t = time.perf_counter()
+        oracle.voxelize_grad(P["mu"], P["scale"], P["quat"], P["density"], g.dims, g.lo, g.inv_h, box, dV)
+        t_grad = time.perf_counter() - t
+        scale = prob.geom.n_views / nv
+        return 1e3 * (t_vox + t_grad + (t_proj + t_bp) * scale), t_vox + t_proj + t_bp + t_grad, scale
+
+    ms, wall, scale = run(n_views_sample)
+    out = {"value": round(ms, 1), "unit": "ms/iter", "cores": nthreads, "kind": "oracle",
+           "sample": (f"binary64 oracle: full voxelization and voxelization gradient "
+                      f"(100k Gaussians, 256^3), projection+L1 and backprojection over "
+                      f"{n_views_sample} of 360 views scaled x{scale:.1f}; {wall:.1f} s wall")}
+    oracle.set_num_threads(1)
+    try:
+        ms1, wall1, scale1 = run(n_views_single)
+    finally:
+        oracle.set_num_threads(nthreads)
+    out["single_thread"] = {"value": round(ms1, 1), "unit": "ms/iter", "cores": 1,
+                            "sample": (f"the same on one thread, projection+L1 and backprojection over "
+                                       f"{n_views_single} of 360 views scaled x{scale1:.0f}; {wall1:.1f} s wall")}
+    return out
+
+
+def large_leg(steps: int = 2):
+    """The 512^3 workload: 500,000 anisotropic Gaussians (scale ratio up to
+    10:1), cone beam 720 views x 1024^2 at 0.4 mm; fwd+bwd+Adam ms per
+    iteration and the peak device memory of the run (the volume is recomputed
+    for the backward pass, never stored)."""
+    from paper_2411_04844_amd import recon
+    torch.cuda.reset_peak_memory_stats()
+    prob = recon.cone_problem(D=512, n=500_000, n_views=720, n_det=1024, pitch_mm=0.4,
+                              seeds=(4001, 4002, 4003), ratio_max=10.0, device="cuda")
+    it = recon.Iteration(prob)
+    it.step()
+    torch.cuda.synchronize()
+    ev = {}
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for i in range(steps):
+        it.step(events=ev)
+        log(f"512^3 step {i + 1}/{steps} enqueued")
+    b.record()
+    torch.cuda.synchronize()
+    it.check()
+    out = {"ms_per_iter": round(a.elapsed_time(b) / steps, 2),
+           "stage_ms": {k: round(float(np.mean([x.elapsed_time(y) for x, y in v])), 2) for k, v in ev.items()},
+           "peak_device_gib": round(torch.cuda.max_memory_allocated() / 2 ** 30, 2),
+           "projection_workspace_gib": round(it.proj_ws.buf.numel() / 2 ** 30, 2),
+           "gaussians": 500_000, "views": 720, "detector": 1024, "volume": 512}
+    del it, prob
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -280,12 +340,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-views", type=int, default=40, help="views in the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--recon", type=int, default=300, metavar="MAX_ITERS",
+    ap.add_argument("--recon", type=int, default=5000, metavar="MAX_ITERS",
                     help="iteration cap of the 25-view sparse loops to 35 dB (0: skip them)")
+    ap.add_argument("--large-steps", type=int, default=2,
+                    help="timed iterations of the 512^3 / 720 x 1024^2 workload (0: skip it)")
+    ap.add_argument("--fan-iters", type=int, default=300,
+                    help="iterations of the fan-beam loops (0: skip them)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
     ap.add_argument("--iteration-only", action="store_true",
                     help="time the iteration and skip every other leg (for profiler runs)")
+    ap.add_argument("--objective", choices=("l1", "full", "both"), default="l1",
+                    help="with --iteration-only: the L1 iteration, the full-objective one, or both")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: there is no multi-GPU path "
@@ -328,16 +394,45 @@ def main():
         f"wall {wall:.2f}s loss {float(it.loss):.6g}")
 
     dom = max(FLOP_PER_SAMPLE, key=lambda k: stage_ms[k])
+    kname = KERNEL_SOURCE[dom]
     achieved = FLOP_PER_SAMPLE[dom] * samples / (stage_ms[dom] * 1e-3) / 1e12
-    traffic = hbm_traffic(KERNEL_SOURCE[dom])
-    roofline = {"kernel": KERNEL_SOURCE[dom], "stage": dom, "bound": "alu",
-                "achieved": round(achieved, 3), "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP32_VALU_PEAK_TFLOPS, 4),
-                "traffic": None if traffic is None else round(traffic)}
+    ctr = committed_counters(kname)
+    roofline = {"kernel": kname, "stage": dom, "bound": "alu",
+                "achieved": round(achieved, 3), "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
+                "traffic": None if ctr is None else round(ctr["hbm_bytes"]),
+                "flop_per_sample": FLOP_PER_SAMPLE[dom], "samples": samples}
+    if ctr is not None and "valu" in ctr:
+        # VALU wave-instructions of one launch (SQ_INSTS_VALU) at the stage's
+        # measured duration, against the single-issue lane rate of the chip
+        lane = ctr["valu"] * 64.0
+        roofline["valu"] = {"lane_instr_per_sample": round(lane / samples, 2),
+                            "lane_instr_per_s": lane / (stage_ms[dom] * 1e-3),
+                            "single_issue_peak": VALU_LANE_INSTR_PER_S,
+                            "frac": round(lane / (stage_ms[dom] * 1e-3) / VALU_LANE_INSTR_PER_S, 4)}
+    # HBM-bound stages: algorithmic bytes over the measured stage time
+    n = prob.params["mu"].shape[0]
+    nvox = int(np.prod(prob.grid.dims))
+    stage_bytes = {"voxelize": 44 * n + 4 * nvox, "voxelize_backward": 44 * n + 4 * nvox + 44 * n,
+                   "adam": 28 * 11 * n}
+    hbm = {k: {"bytes": b, "ms": round(stage_ms[k], 4),
+               "GB/s": round(b / (stage_ms[k] * 1e-3) / 1e9, 1),
+               "frac": round(b / (stage_ms[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)} for k, b in stage_bytes.items()}
 
     if args.iteration_only:
-        print(json.dumps({"metric": METRIC, "value": round(ms, 3), "unit": "ms/iter",
-                          "stage_ms": {k: round(v, 3) for k, v in stage_ms.items()}}), flush=True)
+        line = {"metric": METRIC, "value": round(ms, 3), "unit": "ms/iter",
+                "stage_ms": {k: round(v, 3) for k, v in stage_ms.items()}}
+        if args.objective in ("full", "both"):
+            itf = recon.Iteration(prob, objective="full")
+            ev_f = {}
+            for i in range(args.warmup + args.steps):
+                itf.step(events=ev_f if i >= args.warmup else None)
+                log(f"full-objective step {i + 1}/{args.warmup + args.steps} enqueued")
+            torch.cuda.synchronize()
+            itf.check()
+            line["full_objective_stage_ms"] = {k: round(float(np.mean([a.elapsed_time(b) for a, b in v])), 3)
+                                               for k, v in ev_f.items()}
+        print(json.dumps(line), flush=True)
         return
 
     cpu = None
@@ -361,6 +456,13 @@ def main():
     full = {"ms_per_iter": round(f0.elapsed_time(f1) / 5, 3),
             "stage_ms": {k: round(float(np.mean([a.elapsed_time(b) for a, b in v])), 3) for k, v in ev_f.items()},
             "weights": list(itf.weights)}
+    # projection loss: P_hat and y read, dL/dP_hat written; TV: V read, dL/dV
+    # read and written
+    npix = prob.target.numel()
+    for k, b in (("projection_loss", 12 * npix), ("tv", 12 * nvox)):
+        t = full["stage_ms"][k]
+        hbm[k] = {"bytes": b, "ms": t, "GB/s": round(b / (t * 1e-3) / 1e9, 1),
+                  "frac": round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     del itf
     log("fixed-box voxelization sweep")
     fvr = fvr_leg()
@@ -369,7 +471,11 @@ def main():
         log("sparse-view loop to 35 dB")
         rec = recon_leg(args.recon)
     log("fan-beam settings")
-    fan = fan_leg(args.recon)
+    fan = fan_leg(args.fan_iters)
+    large = None
+    if args.large_steps > 0:
+        log("512^3 / 500k / 720 x 1024^2 iteration")
+        large = large_leg(args.large_steps)
 
     out = {
         "metric": METRIC, "value": round(ms, 3), "unit": "ms/iter", "n_gpus": 1,
@@ -382,12 +488,15 @@ def main():
         "stage_ms": {k: round(v, 3) for k, v in stage_ms.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "hbm_stages": hbm,
     }
     out["full_objective_iteration"] = full
     out["fvr_fixed_box_256^3_150k_isotropic"] = fvr
     if rec is not None:
         out["recon"] = rec
     out["fan_beam"] = fan
+    if large is not None:
+        out["large_512^3_500k_720x1024^2"] = large
     print(json.dumps(out), flush=True)
 
 

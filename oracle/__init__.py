@@ -119,6 +119,8 @@ def lib():
         L.orc_init_from_volume.restype = i64
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [i32]
+        L.orc_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -133,6 +135,11 @@ def _c(a, dtype):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the following oracle calls (OpenMP)."""
+    lib().orc_set_num_threads(int(n))
 
 
 def _grid_args(dims, lo, inv_h, dtype):

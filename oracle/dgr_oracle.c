@@ -703,6 +703,16 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Threads for the following calls (for single-thread timings). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* O9. FDK (Feldkamp-Davis-Kress) for a full circular cone-beam scan on a   */
 /* flat detector, the textbook filtered backprojection (Kak & Slaney, the  */
