@@ -17,11 +17,12 @@
 // position; no periodic re-anchoring is needed.
 // Forward: one thread per ray; the volume is read from a copy with a two-voxel
 // zero border, so the eight taps of any sample in the support need no test.
-// Backward: one work-group per 20 x 20 x 10-cell brick accumulates, over all
-// views, the samples whose trilinear cell lies in the brick into a 21 x 21 x 11
-// LDS tile (flat bricks: for nearly horizontal rays the detector footprint of a
-// brick, and with it the ray set-up, shrinks while the samples per ray grow; no
-// global atomics); the tiles are then summed per voxel.  The LDS sums are
+// Backward: each ray is set up once per view batch into a table row; one
+// work-group per 20 x 20 x 6-cell brick accumulates, over all views, the
+// samples whose trilinear cell lies in the brick into a 21 x 21 x 7 LDS tile
+// (flat bricks: for nearly horizontal rays the detector footprint of a brick
+// shrinks while the samples per ray grow; 37 KB of LDS, four work-groups per
+// CU; no global atomics); the tiles are then summed per voxel.  The LDS sums are
 // 64-bit fixed point: the weights of the samples of one ray in one cell are
 // summed in registers, scaled by a power of two S chosen from max|proj| so that
 // the sum fits in 32 bits, converted to an integer (within one unit) and added
@@ -40,7 +41,22 @@ constexpr int kPad = 2;
 constexpr int kXcd = 8;     // MI355X: work-groups are dealt round-robin to 8 XCDs
 // Backprojection bricks: kBX x kBY x kBZ cells (<= 32 each: 5-bit local
 // cells in the ray records), tiles one voxel larger per axis.
-constexpr int kBX = 20, kBY = 20, kBZ = 10;
+#ifndef DGR_BRICK_X
+#define DGR_BRICK_X 20
+#endif
+#ifndef DGR_BRICK_Y
+#define DGR_BRICK_Y 20
+#endif
+#ifndef DGR_BRICK_Z
+#define DGR_BRICK_Z 6
+#endif
+#ifndef DGR_BP_WAVES
+#define DGR_BP_WAVES 4
+#endif
+#ifndef DGR_BP_XCD
+#define DGR_BP_XCD 0
+#endif
+constexpr int kBX = DGR_BRICK_X, kBY = DGR_BRICK_Y, kBZ = DGR_BRICK_Z;
 constexpr int kTBX = kBX + 1, kTBY = kBY + 1, kTBZ = kBZ + 1;
 constexpr int kBT3 = kTBX * kTBY * kTBZ;
 static_assert(kBX <= 32 && kBY <= 32 && kBZ <= 32, "local cells are 5-bit");
@@ -294,6 +310,9 @@ __device__ __forceinline__ float wave_sum(float v) {
 constexpr int kBun = 16;         // bundle edge (pixels)
 constexpr int kBoxCap = 5600;    // LDS box (cells, 22 KB)
 constexpr int kFwdChunk = 16;    // samples per chunk
+#ifndef DGR_FWD_ODD_PLANE
+#define DGR_FWD_ODD_PLANE 0
+#endif
 
 __device__ __forceinline__ void block_bounds(int v[6], int (*red)[8], int wave, int lane) {
 #pragma unroll
@@ -321,13 +340,14 @@ __device__ __forceinline__ void block_bounds(int v[6], int (*red)[8], int wave, 
 // first LDS write, so the loads overlap.
 template <bool kSmall>
 __device__ __forceinline__ void stage_box(float *box, const float *__restrict__ src, int nx, int ny, int nz,
-                                          unsigned px, unsigned plane) {
+                                          unsigned px, unsigned plane, int zpad) {
     const int n = nx * ny * nz;
     const float inx = 1.0f / (float)nx, iny = 1.0f / (float)ny;
     const float hnx = 0.5f * inx, hny = 0.5f * iny;  // exact halves
     constexpr int kStage = 4;
     for (int q0 = threadIdx.x; q0 < n; q0 += 256 * kStage) {
         float v[kStage];
+        int lzs[kStage];
 #pragma unroll
         for (int u = 0; u < kStage; ++u) {
             const int q = q0 + u * 256;
@@ -338,11 +358,12 @@ __device__ __forceinline__ void stage_box(float *box, const float *__restrict__ 
                 const unsigned off = kSmall ? __umul24((unsigned)lz, plane) + __umul24((unsigned)ly, px) + (unsigned)lx
                                             : (unsigned)lz * plane + (unsigned)ly * px + (unsigned)lx;
                 v[u] = src[off];
+                lzs[u] = lz;
             }
         }
 #pragma unroll
         for (int u = 0; u < kStage; ++u)
-            if (q0 + u * 256 < n) box[q0 + u * 256] = v[u];
+            if (q0 + u * 256 < n) box[q0 + u * 256 + lzs[u] * zpad] = v[u];
     }
 }
 
@@ -399,16 +420,19 @@ __global__ __launch_bounds__(256) void project_bundles(const float *__restrict__
         if (bb[0] > bb[3]) continue;
         const int o[3] = {bb[0], bb[1], bb[2]};
         const int nx = bb[3] - bb[0] + 2, ny = bb[4] - bb[1] + 2, nz = bb[5] - bb[2] + 2;
-        if ((int64_t)nx * ny * nz <= kBoxCap) {
+        // plane pitch of the LDS box (odd with DGR_FWD_ODD_PLANE: lanes whose
+        // taps differ only in z then fall in different banks)
+        const int bsz = DGR_FWD_ODD_PLANE ? ((nx * ny) | 1) : nx * ny;
+        if ((int64_t)bsz * nz <= kBoxCap) {
             // taps of the chunk: padded voxels o .. o + n - 1, inside the padded
             // copy
             const float *src = vp + ((int64_t)o[2] * p.py + o[1]) * p.px + o[0];
             if (p.plane < (int64_t(1) << 24))
-                stage_box<true>(box, src, nx, ny, nz, (unsigned)p.px, (unsigned)p.plane);
+                stage_box<true>(box, src, nx, ny, nz, (unsigned)p.px, (unsigned)p.plane, bsz - nx * ny);
             else
-                stage_box<false>(box, src, nx, ny, nz, (unsigned)p.px, (unsigned)p.plane);
+                stage_box<false>(box, src, nx, ny, nz, (unsigned)p.px, (unsigned)p.plane, bsz - nx * ny);
             __syncthreads();
-            if (has) march_box(box, nx, nx * ny, o, r, a, e, acc);
+            if (has) march_box(box, nx, bsz, o, r, a, e, acc);
             __syncthreads();
         } else if (has) {
             const int o0[3] = {0, 0, 0};
@@ -532,7 +556,7 @@ __device__ __forceinline__ double fixed_scale(const unsigned *maxbits, float sca
 // ---- per-ray table of the backprojection -------------------------------------
 // Every ray is set up once per view batch (binary64 geometry, fixed-point
 // anchor and advance, the scaled projection value) and read by each brick its
-// shadow rectangle holds, instead of once per brick (a ray crosses about 20
+// shadow rectangle holds, instead of once per brick (a ray crosses about 30
 // bricks of the 256^3 workload).  48 bytes per ray, 16-byte aligned.
 struct alignas(16) RayTab {
     long long U[3];   // anchor, padded voxel coordinates, 32.32 fixed point
@@ -772,9 +796,9 @@ __device__ __forceinline__ void march_segments(unsigned long long *tile, const R
 
 // seg_shift: log2 of the samples per segment, chosen on the host so that no ray
 // in a brick has more than kMaxSeg segments (and no more than 256 samples).
-// Three work-groups per CU (51 KB of LDS each, <= 168 VGPRs): the extra waves
+// Four work-groups per CU (37 KB of LDS each, <= 128 VGPRs): the extra waves
 // overlap one work-group's LDS adds with another's arithmetic.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void backproject_bricks(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DGR_BP_WAVES, DGR_BP_WAVES))) void backproject_bricks(
     const RayTab *__restrict__ tab, int j0, int nj, GeomDev G, Bricks bk, const ushort4 *__restrict__ rect,
     int seg_shift, int accumulate, long long *__restrict__ staging) {
     __shared__ unsigned long long tile[kBT3];
@@ -782,8 +806,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     __shared__ unsigned short segs[kSegCap];
     __shared__ int q_rays, q_segs;
     const int t = threadIdx.x, lane = t & 63;
-    const int64_t b = blockIdx.x;
     const int64_t nb = bk.count();
+#if DGR_BP_XCD
+    // each XCD (every 8th dispatched work-group) takes a contiguous range of
+    // bricks, so the bricks sharing its L2 are neighbours and read the same
+    // detector rows of the ray table
+    const int64_t per_xcd = (nb + kXcd - 1) / kXcd;
+    const int64_t b = (int64_t)(blockIdx.x % kXcd) * per_xcd + blockIdx.x / kXcd;
+    if (b >= nb) return;  // whole work-group
+#else
+    const int64_t b = blockIdx.x;
+    if (b >= nb) return;  // whole work-group (the launch is rounded up to 8)
+#endif
     const int bx = (int)(b % bk.nx), by = (int)((b / bk.nx) % bk.ny), bz = (int)(b / ((int64_t)bk.nx * bk.ny));
     // brick cells in padded coordinates: [c0, c0 + kB)
     const int c0x = bx * kBX - 1 + kPad, c0y = by * kBY - 1 + kPad, c0z = bz * kBZ - 1 + kPad;
@@ -1147,7 +1181,8 @@ extern "C" dgr_status dgr_backproject(const float *proj, const dgr_grid *grid,
         ray_table<<<dim3((unsigned)((nrays + 255) / 256)), dim3(256), 0, st>>>(proj, G, g, j0, nrays, w.maxbits,
                                                                               headroom, w.tab);
         DGR_LAUNCH_CHECK();
-        backproject_bricks<<<dim3((unsigned)bk.count()), dim3(256), 0, st>>>(w.tab, j0, nj, G, bk, w.rect,
+        backproject_bricks<<<dim3((unsigned)((bk.count() + kXcd - 1) / kXcd * kXcd)), dim3(256), 0, st>>>(
+            w.tab, j0, nj, G, bk, w.rect,
                                                                              seg_shift, j0 > 0 ? 1 : 0,
                                                                              w.staging);
         DGR_LAUNCH_CHECK();

@@ -2,12 +2,15 @@
 // V(p) = sum_g rho_g exp(-1/2 d^T Q_g d), d = p - mu_g, over the voxel centres
 // p in each Gaussian's truncation box.
 //
-// One 256-thread work-group owns one 8^3 tile; each thread owns two voxels
-// (z and z+4) and keeps their sums in registers.  The tile's Gaussians arrive
-// as a gid-sorted list from the binning step; they are staged through LDS in
-// chunks of 256, converted to tile-relative coordinates, and added in list
-// order, so the result does not depend on scheduling.  The quadratic form uses
-// the paper's split of the position into the floored anchor and its residual
+// One wavefront owns one 8^3 tile (four per work-group); each lane owns one
+// row of 8 voxels along x (lane = 8 z + y) and keeps their sums in registers.
+// The tile's Gaussians arrive as a gid-sorted list from the binning step and
+// are read wave-uniformly (through the scalar cache) and added in list order,
+// so the result does not depend on scheduling.  Per Gaussian only the rows
+// inside its box take part, and only the x range of the box within the tile
+// is evaluated: the exponent along a row is a quadratic in dx,
+// e = base(dy, dz) + dx (k00 dx + b(dy, dz)).  The quadratic form uses the
+// paper's split of the position into the floored anchor and its residual
 // (Discretize and Align, sec. 4.1): d = (i - floor(u)) - (u - floor(u)), which
 // keeps d accurate to ~1e-6 voxel in binary32 on large grids.
 #include <algorithm>
@@ -17,76 +20,58 @@
 namespace dgr {
 namespace {
 
-struct alignas(16) TileRec {
-    float ux, uy, uz, rho;
-    float k00, k11, k22, k01;
-    float k02, k12;
-    int bx0, bx1, by0, by1, bz0, bz1;
-};
-static_assert(sizeof(TileRec) == 64, "tile record must be 64 bytes");
-
 __global__ __launch_bounds__(256) void voxelize_tiles(const GaussRec *__restrict__ rec,
                                                       const uint32_t *__restrict__ gid,
                                                       const uint32_t *__restrict__ tile_begin,
                                                       const VoxHeader *__restrict__ hdr,
-                                                      int64_t cap, DevGrid g, int Tx, int Ty,
+                                                      int64_t cap, int64_t tiles, DevGrid g, int Tx, int Ty,
                                                       float *__restrict__ V) {
-    __shared__ TileRec S[256];
-    const int64_t tile = blockIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int64_t tile = (int64_t)blockIdx.x * 4 + wave;
+    if (tile >= tiles) return;  // whole wavefront
+    const int lane = threadIdx.x & 63;
     const int tx = (int)(tile % Tx), ty = (int)((tile / Tx) % Ty), tz = (int)(tile / ((int64_t)Tx * Ty));
     const int ox = tx * 8, oy = ty * 8, oz = tz * 8;
-    const int t = threadIdx.x;
-    const int lx = t & 7, ly = (t >> 3) & 7, lz = t >> 6;
-    const float fx = (float)lx, fy = (float)ly, fz0 = (float)lz, fz1 = (float)(lz + 4);
-    const int64_t vx = ox + lx, vy = oy + ly, vz0 = oz + lz, vz1 = oz + lz + 4;
+    const int ly = lane & 7, lz = lane >> 3;
+    const int vy = oy + ly, vz = oz + lz;
     const int64_t plane = (int64_t)g.nx * g.ny;
-    const bool store_xy = vx < g.nx && vy < g.ny;
+    const bool row_in = vy < g.ny && vz < g.nz;
+    float *row = V + (int64_t)vz * plane + (int64_t)vy * g.nx + ox;
+    const int nxr = min(8, g.nx - ox);  // voxels of the row inside the grid
 
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (hdr->total > (uint64_t)cap) {  // pair list incomplete: poison the tile
         const float nan = __builtin_nanf("");
-        if (store_xy && vz0 < g.nz) V[vz0 * plane + vy * g.nx + vx] = nan;
-        if (store_xy && vz1 < g.nz) V[vz1 * plane + vy * g.nx + vx] = nan;
-        return;
-    }
-    const uint32_t beg = tile_begin[tile], end = tile_begin[tile + 1];
-    float acc0 = 0.0f, acc1 = 0.0f;
-    for (uint32_t c = beg; c < end; c += 256) {
-        const int m = (int)min<uint32_t>(256u, end - c);
-        if (t < m) {
-            const GaussRec r = rec[gid[c + t]];
-            TileRec s;
-            s.ux = (float)(r.ui[0] - ox) + r.uf[0];
-            s.uy = (float)(r.ui[1] - oy) + r.uf[1];
-            s.uz = (float)(r.ui[2] - oz) + r.uf[2];
-            s.rho = r.rho;
-            s.k00 = r.k00; s.k11 = r.k11; s.k22 = r.k22;
-            s.k01 = r.k01; s.k02 = r.k02; s.k12 = r.k12;
-            s.bx0 = box_lo(r.box[0]) - ox; s.bx1 = box_hi(r.box[0]) - ox;
-            s.by0 = box_lo(r.box[1]) - oy; s.by1 = box_hi(r.box[1]) - oy;
-            s.bz0 = box_lo(r.box[2]) - oz; s.bz1 = box_hi(r.box[2]) - oz;
-            S[t] = s;
-        }
-        __syncthreads();
-        for (int j = 0; j < m; ++j) {
-            const TileRec &s = S[j];
-            const bool inxy = lx >= s.bx0 && lx <= s.bx1 && ly >= s.by0 && ly <= s.by1;
-            const bool in0 = inxy && lz >= s.bz0 && lz <= s.bz1;
-            const bool in1 = inxy && lz + 4 >= s.bz0 && lz + 4 <= s.bz1;
-            if (in0 || in1) {
-                const float dx = fx - s.ux, dy = fy - s.uy;
-                const float exy = dx * (s.k00 * dx + s.k01 * dy) + s.k11 * dy * dy;
-                const float lin = s.k02 * dx + s.k12 * dy;
-                const float dz0 = fz0 - s.uz, dz1 = fz1 - s.uz;
-                const float e0 = exy + dz0 * (lin + s.k22 * dz0);
-                const float e1 = exy + dz1 * (lin + s.k22 * dz1);
-                if (in0) acc0 += s.rho * __builtin_amdgcn_exp2f(e0);
-                if (in1) acc1 += s.rho * __builtin_amdgcn_exp2f(e1);
+#pragma unroll
+        for (int x = 0; x < 8; ++x) acc[x] = nan;
+    } else {
+        const uint32_t beg = tile_begin[tile], end = tile_begin[tile + 1];
+        for (uint32_t c = beg; c < end; ++c) {
+            const uint32_t gi = __builtin_amdgcn_readfirstlane(gid[c]);
+            const GaussRec r = rec[gi];
+            const int by0 = box_lo(r.box[1]), by1 = box_hi(r.box[1]);
+            const int bz0 = box_lo(r.box[2]), bz1 = box_hi(r.box[2]);
+            // x range of the box inside the tile (uniform over the wave)
+            const int xa = max(box_lo(r.box[0]) - ox, 0), xb = min(box_hi(r.box[0]) - ox, 7);
+            if (vy < by0 || vy > by1 || vz < bz0 || vz > bz1 || xa > xb) continue;
+            const float dy = (float)(vy - r.ui[1]) - r.uf[1];
+            const float dz = (float)(vz - r.ui[2]) - r.uf[2];
+            const float base = dy * (r.k11 * dy + r.k12 * dz) + r.k22 * dz * dz;
+            const float bl = r.k01 * dy + r.k02 * dz;
+            const float dx0 = (float)(ox - r.ui[0]) - r.uf[0];
+#pragma unroll
+            for (int x = 0; x < 8; ++x) {
+                if (x >= xa && x <= xb) {  // uniform
+                    const float dx = dx0 + (float)x;
+                    acc[x] += r.rho * __builtin_amdgcn_exp2f(base + dx * (r.k00 * dx + bl));
+                }
             }
         }
-        __syncthreads();
     }
-    if (store_xy && vz0 < g.nz) V[vz0 * plane + vy * g.nx + vx] = acc0;
-    if (store_xy && vz1 < g.nz) V[vz1 * plane + vy * g.nx + vx] = acc1;
+    if (!row_in) return;
+#pragma unroll
+    for (int x = 0; x < 8; ++x)
+        if (x < nxr) row[x] = acc[x];
 }
 
 dgr_status check_vox_args(const float *mu, const float *scale, const float *quat, int64_t n,
@@ -159,8 +144,8 @@ extern "C" dgr_status dgr_voxelize(const float *mu, const float *scale, const fl
     if ((s = enqueue_binning(mu, scale, quat, density, n, grid, trunc, w, &which, st)) != DGR_OK)
         return s;
     const int Tx = (grid->dims[0] + 7) / 8, Ty = (grid->dims[1] + 7) / 8;
-    voxelize_tiles<<<dim3((unsigned)w.tiles), dim3(256), 0, st>>>(
-        w.rec, w.val[which], w.tile_begin, w.hdr, w.cap, dev_grid(grid), Tx, Ty, volume);
+    voxelize_tiles<<<dim3((unsigned)((w.tiles + 3) / 4)), dim3(256), 0, st>>>(
+        w.rec, w.val[which], w.tile_begin, w.hdr, w.cap, w.tiles, dev_grid(grid), Tx, Ty, volume);
     DGR_LAUNCH_CHECK();
     return DGR_OK;
 }

@@ -10,9 +10,11 @@
 //   Q = R diag(s^-2) R^T:  ds_j = -2 s_j^-3 (R^T dQ R)_jj,  dR = 2 dQ R diag(s^-2),
 //   dq = (I - q_hat q_hat^T) (dR : dR/dq_hat) / |q|.
 // One wavefront owns one Gaussian: its lanes stride the box (x fastest, so
-// reads of dL/dV are row-coalesced), accumulate the ten moments in registers,
-// reduce them across the wavefront with shuffles, and lane 0 applies the chain
-// rule in binary64.  No atomics; the result is deterministic.
+// reads of dL/dV are row-coalesced), accumulate the ten moments in registers
+// and reduce them across the wavefront (DPP); lane 0 stores them in the
+// Gaussian's record slot.  A second kernel applies the chain rule in binary64
+// with one thread per Gaussian, so the serial binary64 work no longer holds a
+// whole wavefront.  No atomics; the result is deterministic.
 #include <mutex>
 
 #include "internal.h"
@@ -42,10 +44,16 @@ __device__ __forceinline__ float wave_sum(float v) {
            (__int_as_float(__builtin_amdgcn_readlane(b, 32)) + __int_as_float(__builtin_amdgcn_readlane(b, 48)));
 }
 
-__global__ __launch_bounds__(256) void voxelize_grad(
-    const GaussRec *__restrict__ rec, int64_t n, const float *__restrict__ dV, DevGrid g,
-    const float *__restrict__ scale, const float *__restrict__ quat, float *__restrict__ dmu,
-    float *__restrict__ dscale, float *__restrict__ dquat, float *__restrict__ ddensity) {
+// The ten moments of one Gaussian and its density (44 bytes, inside the
+// 64-byte slot of its record).
+struct GaussMoments {
+    float m[10];  // M0, m1 (x, y, z), M2 (xx, yy, zz, xy, xz, yz), voxel units
+    float rho;
+};
+static_assert(sizeof(GaussMoments) <= sizeof(GaussRec), "moments must fit the record slot");
+
+__global__ __launch_bounds__(256) void voxelize_grad(GaussRec *__restrict__ rec, int64_t n,
+                                                     const float *__restrict__ dV, DevGrid g) {
     const int64_t gi = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (gi >= n) return;
@@ -86,9 +94,28 @@ __global__ __launch_bounds__(256) void voxelize_grad(
     m1x = wave_sum(m1x); m1y = wave_sum(m1y); m1z = wave_sum(m1z);
     Mxx = wave_sum(Mxx); Myy = wave_sum(Myy); Mzz = wave_sum(Mzz);
     Mxy = wave_sum(Mxy); Mxz = wave_sum(Mxz); Myz = wave_sum(Myz);
-    if (lane != 0) return;
+    // The ten moments replace the Gaussian's record (its wave has read it);
+    // chain_rule turns them into gradients with one lane per Gaussian.
+    if (lane == 0) {
+        GaussMoments mo;
+        mo.m[0] = M0; mo.m[1] = m1x; mo.m[2] = m1y; mo.m[3] = m1z;
+        mo.m[4] = Mxx; mo.m[5] = Myy; mo.m[6] = Mzz; mo.m[7] = Mxy; mo.m[8] = Mxz; mo.m[9] = Myz;
+        mo.rho = r.rho;
+        reinterpret_cast<GaussMoments *>(rec)[gi] = mo;
+    }
+}
 
-    // ---- chain rule in binary64, world units ----
+// Chain rule in binary64, world units, one thread per Gaussian, from the
+// moments voxelize_grad left in the record slots.
+__global__ __launch_bounds__(256) void chain_rule(const GaussRec *__restrict__ rec, int64_t n, DevGrid g,
+                                                  const float *__restrict__ scale, const float *__restrict__ quat,
+                                                  float *__restrict__ dmu, float *__restrict__ dscale,
+                                                  float *__restrict__ dquat, float *__restrict__ ddensity) {
+    const int64_t gi = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (gi >= n) return;
+    const GaussMoments mo = reinterpret_cast<const GaussMoments *>(rec)[gi];
+    const float M0 = mo.m[0], m1x = mo.m[1], m1y = mo.m[2], m1z = mo.m[3];
+    const float Mxx = mo.m[4], Myy = mo.m[5], Mzz = mo.m[6], Mxy = mo.m[7], Mxz = mo.m[8], Myz = mo.m[9];
     const double ih[3] = {g.inv_h[0], g.inv_h[1], g.inv_h[2]};
     const double m1[3] = {m1x / ih[0], m1y / ih[1], m1z / ih[2]};
     double M2[3][3];
@@ -117,7 +144,7 @@ __global__ __launch_bounds__(256) void voxelize_grad(
     for (int a = 0; a < 3; ++a)
         for (int b = 0; b < 3; ++b)
             Q[a][b] = R[a][0] * R[b][0] * lam[0] + R[a][1] * R[b][1] * lam[1] + R[a][2] * R[b][2] * lam[2];
-    const double rho = r.rho;
+    const double rho = mo.rho;
     ddensity[gi] = M0;
     for (int a = 0; a < 3; ++a)
         dmu[3 * gi + a] = (float)(rho * (Q[a][0] * m1[0] + Q[a][1] * m1[1] + Q[a][2] * m1[2]));
@@ -204,8 +231,10 @@ dgr_status launch_backward(const float *mu, const float *scale, const float *qua
     dgr_status s;
     if ((s = launch_prep(mu, scale, quat, density, n, grid, trunc, rec, nullptr, nullptr, st)) != DGR_OK)
         return s;
-    voxelize_grad<<<dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st>>>(
-        rec, n, dvolume, dev_grid(grid), scale, quat, dmu, dscale, dquat, ddensity);
+    voxelize_grad<<<dim3((unsigned)((n + 3) / 4)), dim3(256), 0, st>>>(rec, n, dvolume, dev_grid(grid));
+    DGR_LAUNCH_CHECK();
+    chain_rule<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(rec, n, dev_grid(grid), scale, quat, dmu,
+                                                                        dscale, dquat, ddensity);
     DGR_LAUNCH_CHECK();
     return DGR_OK;
 }
