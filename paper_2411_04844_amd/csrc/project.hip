@@ -53,9 +53,6 @@ constexpr int kXcd = 8;     // MI355X: work-groups are dealt round-robin to 8 XC
 #ifndef DGR_BP_WAVES
 #define DGR_BP_WAVES 4
 #endif
-#ifndef DGR_BP_XCD
-#define DGR_BP_XCD 0
-#endif
 constexpr int kBX = DGR_BRICK_X, kBY = DGR_BRICK_Y, kBZ = DGR_BRICK_Z;
 constexpr int kTBX = kBX + 1, kTBY = kBY + 1, kTBZ = kBZ + 1;
 constexpr int kBT3 = kTBX * kTBY * kTBZ;
@@ -310,9 +307,6 @@ __device__ __forceinline__ float wave_sum(float v) {
 constexpr int kBun = 16;         // bundle edge (pixels)
 constexpr int kBoxCap = 5600;    // LDS box (cells, 22 KB)
 constexpr int kFwdChunk = 16;    // samples per chunk
-#ifndef DGR_FWD_ODD_PLANE
-#define DGR_FWD_ODD_PLANE 0
-#endif
 
 __device__ __forceinline__ void block_bounds(int v[6], int (*red)[8], int wave, int lane) {
 #pragma unroll
@@ -340,14 +334,13 @@ __device__ __forceinline__ void block_bounds(int v[6], int (*red)[8], int wave, 
 // first LDS write, so the loads overlap.
 template <bool kSmall>
 __device__ __forceinline__ void stage_box(float *box, const float *__restrict__ src, int nx, int ny, int nz,
-                                          unsigned px, unsigned plane, int zpad) {
+                                          unsigned px, unsigned plane) {
     const int n = nx * ny * nz;
     const float inx = 1.0f / (float)nx, iny = 1.0f / (float)ny;
     const float hnx = 0.5f * inx, hny = 0.5f * iny;  // exact halves
     constexpr int kStage = 4;
     for (int q0 = threadIdx.x; q0 < n; q0 += 256 * kStage) {
         float v[kStage];
-        int lzs[kStage];
 #pragma unroll
         for (int u = 0; u < kStage; ++u) {
             const int q = q0 + u * 256;
@@ -358,12 +351,11 @@ __device__ __forceinline__ void stage_box(float *box, const float *__restrict__ 
                 const unsigned off = kSmall ? __umul24((unsigned)lz, plane) + __umul24((unsigned)ly, px) + (unsigned)lx
                                             : (unsigned)lz * plane + (unsigned)ly * px + (unsigned)lx;
                 v[u] = src[off];
-                lzs[u] = lz;
             }
         }
 #pragma unroll
         for (int u = 0; u < kStage; ++u)
-            if (q0 + u * 256 < n) box[q0 + u * 256 + lzs[u] * zpad] = v[u];
+            if (q0 + u * 256 < n) box[q0 + u * 256] = v[u];
     }
 }
 
@@ -420,19 +412,16 @@ __global__ __launch_bounds__(256) void project_bundles(const float *__restrict__
         if (bb[0] > bb[3]) continue;
         const int o[3] = {bb[0], bb[1], bb[2]};
         const int nx = bb[3] - bb[0] + 2, ny = bb[4] - bb[1] + 2, nz = bb[5] - bb[2] + 2;
-        // plane pitch of the LDS box (odd with DGR_FWD_ODD_PLANE: lanes whose
-        // taps differ only in z then fall in different banks)
-        const int bsz = DGR_FWD_ODD_PLANE ? ((nx * ny) | 1) : nx * ny;
-        if ((int64_t)bsz * nz <= kBoxCap) {
+        if ((int64_t)nx * ny * nz <= kBoxCap) {
             // taps of the chunk: padded voxels o .. o + n - 1, inside the padded
             // copy
             const float *src = vp + ((int64_t)o[2] * p.py + o[1]) * p.px + o[0];
             if (p.plane < (int64_t(1) << 24))
-                stage_box<true>(box, src, nx, ny, nz, (unsigned)p.px, (unsigned)p.plane, bsz - nx * ny);
+                stage_box<true>(box, src, nx, ny, nz, (unsigned)p.px, (unsigned)p.plane);
             else
-                stage_box<false>(box, src, nx, ny, nz, (unsigned)p.px, (unsigned)p.plane, bsz - nx * ny);
+                stage_box<false>(box, src, nx, ny, nz, (unsigned)p.px, (unsigned)p.plane);
             __syncthreads();
-            if (has) march_box(box, nx, bsz, o, r, a, e, acc);
+            if (has) march_box(box, nx, nx * ny, o, r, a, e, acc);
             __syncthreads();
         } else if (has) {
             const int o0[3] = {0, 0, 0};
@@ -568,9 +557,10 @@ struct alignas(16) RayTab {
 };
 static_assert(sizeof(RayTab) == 48, "ray table rows are 48 bytes");
 constexpr unsigned kRayMiss = 0x80000000u;
-// Table budget per batch of views (bytes); larger scans are backprojected in
-// several batches that add into the same integer tiles.
-constexpr int64_t kRayTableBudget = int64_t(4) << 30;
+// Table budget per batch of views (bytes): 360 views of 512^2 fit one batch;
+// larger scans are backprojected in several batches that add into the same
+// integer tiles.
+constexpr int64_t kRayTableBudget = int64_t(6) << 30;
 
 __global__ __launch_bounds__(256) void ray_table(const float *__restrict__ proj, GeomDev G, DevGrid g,
                                                  int j0, int64_t nrays, const unsigned *__restrict__ maxbits,
@@ -807,17 +797,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DGR_BP_WAVE
     __shared__ int q_rays, q_segs;
     const int t = threadIdx.x, lane = t & 63;
     const int64_t nb = bk.count();
-#if DGR_BP_XCD
-    // each XCD (every 8th dispatched work-group) takes a contiguous range of
-    // bricks, so the bricks sharing its L2 are neighbours and read the same
-    // detector rows of the ray table
-    const int64_t per_xcd = (nb + kXcd - 1) / kXcd;
-    const int64_t b = (int64_t)(blockIdx.x % kXcd) * per_xcd + blockIdx.x / kXcd;
-    if (b >= nb) return;  // whole work-group
-#else
     const int64_t b = blockIdx.x;
-    if (b >= nb) return;  // whole work-group (the launch is rounded up to 8)
-#endif
     const int bx = (int)(b % bk.nx), by = (int)((b / bk.nx) % bk.ny), bz = (int)(b / ((int64_t)bk.nx * bk.ny));
     // brick cells in padded coordinates: [c0, c0 + kB)
     const int c0x = bx * kBX - 1 + kPad, c0y = by * kBY - 1 + kPad, c0z = bz * kBZ - 1 + kPad;
@@ -1181,8 +1161,7 @@ extern "C" dgr_status dgr_backproject(const float *proj, const dgr_grid *grid,
         ray_table<<<dim3((unsigned)((nrays + 255) / 256)), dim3(256), 0, st>>>(proj, G, g, j0, nrays, w.maxbits,
                                                                               headroom, w.tab);
         DGR_LAUNCH_CHECK();
-        backproject_bricks<<<dim3((unsigned)((bk.count() + kXcd - 1) / kXcd * kXcd)), dim3(256), 0, st>>>(
-            w.tab, j0, nj, G, bk, w.rect,
+        backproject_bricks<<<dim3((unsigned)bk.count()), dim3(256), 0, st>>>(w.tab, j0, nj, G, bk, w.rect,
                                                                              seg_shift, j0 > 0 ? 1 : 0,
                                                                              w.staging);
         DGR_LAUNCH_CHECK();
