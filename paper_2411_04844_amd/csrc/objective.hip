@@ -13,7 +13,10 @@
 //   dL_SSIM/dx = -(1/M) [G*(dS/dm1) + 2x G*(dS/dm2) + y G*(dS/dmxy)]
 // (the window is symmetric, so blurring is its own adjoint).  Variances are
 // differences of second moments of line integrals of order 10, which cancel
-// in binary32; the moments, the maps and their blur are binary64.
+// in binary32, so the moments and the SSIM terms are binary64.  The three
+// maps (dS/dm1, dS/dm2, dS/dmxy, order 1/R) are stored and blurred in
+// binary32: they need no cancellation, and halving their bytes halves the
+// traffic between the two passes.
 //
 // Kernels, all HBM-bound stencils: ssim_fwd (one work-group per 32 x 16
 // pixel tile with an 11-pixel halo in LDS: moments, SSIM, the three maps,
@@ -34,6 +37,9 @@ constexpr int kObjBlocks = 1024;
 
 struct Win {
     double w[kWin];
+};
+struct WinF {
+    float w[kWin];
 };
 
 Win gauss_window() {
@@ -90,7 +96,7 @@ __global__ __launch_bounds__(256) void max_final(const float *__restrict__ part,
 // grid (tiles_u, tiles_v, n_views)
 __global__ __launch_bounds__(256) void ssim_fwd(const float *__restrict__ x, const float *__restrict__ y, int nv,
                                                 int nu, Win W, const double *__restrict__ rng, float g1,
-                                                double *__restrict__ maps, int64_t M, float *__restrict__ dproj,
+                                                float *__restrict__ maps, int64_t M, float *__restrict__ dproj,
                                                 double *__restrict__ part) {
     __shared__ float sx[kHY][kHX], sy[kHY][kHX];
     __shared__ double hs[5][kHY][kTX];
@@ -142,9 +148,9 @@ __global__ __launch_bounds__(256) void ssim_fwd(const float *__restrict__ x, con
         const double D = (m[2] - mx * mx) + (m[3] - my * my) + C2;
         const double S = A * B / (Cc * D);
         const int64_t pix = ((int64_t)j * nv + iv) * nu + iu;
-        maps[pix] = S * (2.0 * my / A - 2.0 * my / B - 2.0 * mx / Cc + 2.0 * mx / D);
-        maps[M + pix] = -S / D;
-        maps[2 * M + pix] = 2.0 * S / B;
+        maps[pix] = (float)(S * (2.0 * my / A - 2.0 * my / B - 2.0 * mx / Cc + 2.0 * mx / D));
+        maps[M + pix] = (float)(-S / D);
+        maps[2 * M + pix] = (float)(2.0 * S / B);
         const float res = sx[r + kHalf][c + kHalf] - sy[r + kHalf][c + kHalf];
         dproj[pix] = res > 0.0f ? g1 : (res < 0.0f ? -g1 : 0.0f);
         s_abs += fabs((double)res);
@@ -160,11 +166,11 @@ __global__ __launch_bounds__(256) void ssim_fwd(const float *__restrict__ x, con
 }
 
 // dproj += g2 * (G*a + 2 x G*b + y G*c), g2 = -w2 / M
-__global__ __launch_bounds__(256) void ssim_bwd(const double *__restrict__ maps, int64_t M, const float *__restrict__ x,
-                                                const float *__restrict__ y, int nv, int nu, Win W, double g2,
+__global__ __launch_bounds__(256) void ssim_bwd(const float *__restrict__ maps, int64_t M, const float *__restrict__ x,
+                                                const float *__restrict__ y, int nv, int nu, WinF W, double g2,
                                                 float *__restrict__ dproj) {
-    __shared__ double sm[3][kHY][kHX];
-    __shared__ double hs[3][kHY][kTX];
+    __shared__ float sm[3][kHY][kHX];
+    __shared__ float hs[3][kHY][kTX];
     const int t = threadIdx.x;
     const int j = blockIdx.z;
     const int u0 = blockIdx.x * kTX - kHalf, v0 = blockIdx.y * kTY - kHalf;
@@ -175,12 +181,12 @@ __global__ __launch_bounds__(256) void ssim_bwd(const double *__restrict__ maps,
         const bool in = iv >= 0 && iu >= 0 && iv < nv && iu < nu;
         const int64_t pix = base + (int64_t)iv * nu + iu;
 #pragma unroll
-        for (int q = 0; q < 3; ++q) sm[q][r][c] = in ? maps[q * M + pix] : 0.0;
+        for (int q = 0; q < 3; ++q) sm[q][r][c] = in ? maps[q * M + pix] : 0.0f;
     }
     __syncthreads();
     for (int e = t; e < kHY * kTX; e += 256) {
         const int r = e / kTX, c = e - r * kTX;
-        double m[3] = {0, 0, 0};
+        float m[3] = {0.f, 0.f, 0.f};
 #pragma unroll
         for (int k = 0; k < kWin; ++k)
 #pragma unroll
@@ -193,14 +199,14 @@ __global__ __launch_bounds__(256) void ssim_bwd(const double *__restrict__ maps,
         const int r = e / kTX, c = e - r * kTX;
         const int iv = v0 + kHalf + r, iu = u0 + kHalf + c;
         if (iv >= nv || iu >= nu) continue;
-        double m[3] = {0, 0, 0};
+        float m[3] = {0.f, 0.f, 0.f};
 #pragma unroll
         for (int k = 0; k < kWin; ++k)
 #pragma unroll
             for (int q = 0; q < 3; ++q) m[q] += W.w[k] * hs[q][r + k][c];
         const int64_t pix = base + (int64_t)iv * nu + iu;
         const double xv = x[pix], yv = y[pix];
-        dproj[pix] = (float)((double)dproj[pix] + g2 * (m[0] + 2.0 * xv * m[1] + yv * m[2]));
+        dproj[pix] = (float)((double)dproj[pix] + g2 * ((double)m[0] + 2.0 * xv * (double)m[1] + yv * (double)m[2]));
     }
 }
 
@@ -274,7 +280,7 @@ extern "C" size_t dgr_projection_loss_workspace(int32_t n_views, int32_t nv, int
     const int64_t M = (int64_t)n_views * nv * nu;
     const int64_t tiles = (int64_t)((nu + kTX - 1) / kTX) * ((nv + kTY - 1) / kTY) * n_views;
     Carver c(nullptr);
-    c.take<double>(3 * M);
+    c.take<float>(3 * M);
     c.take<double>(2 * tiles);
     c.take<float>(kObjBlocks);
     c.take<double>(1);
@@ -295,7 +301,7 @@ extern "C" dgr_status dgr_projection_loss(const float *proj, const float *target
     const dim3 grid((unsigned)((nu + kTX - 1) / kTX), (unsigned)((nv + kTY - 1) / kTY), (unsigned)n_views);
     const int64_t tiles = (int64_t)grid.x * grid.y * grid.z;
     Carver c(ws);
-    double *maps = c.take<double>(3 * M);
+    float *maps = c.take<float>(3 * M);
     double *part = c.take<double>(2 * tiles);
     float *mpart = c.take<float>(kObjBlocks);
     double *rng = c.take<double>(1);
@@ -308,7 +314,9 @@ extern "C" dgr_status dgr_projection_loss(const float *proj, const float *target
     ssim_fwd<<<grid, 256, 0, st>>>(proj, target, nv, nu, W, rng, (float)((double)w_l1 / (double)M), maps, M, dproj,
                                    part);
     DGR_LAUNCH_CHECK();
-    ssim_bwd<<<grid, 256, 0, st>>>(maps, M, proj, target, nv, nu, W, -(double)w_ssim / (double)M, dproj);
+    WinF Wf;
+    for (int k = 0; k < kWin; ++k) Wf.w[k] = (float)W.w[k];
+    ssim_bwd<<<grid, 256, 0, st>>>(maps, M, proj, target, nv, nu, Wf, -(double)w_ssim / (double)M, dproj);
     DGR_LAUNCH_CHECK();
     ssim_final<<<1, 256, 0, st>>>(part, (int)tiles, M, w_l1, w_ssim, loss);
     DGR_LAUNCH_CHECK();
