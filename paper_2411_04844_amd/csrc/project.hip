@@ -495,7 +495,9 @@ __global__ __launch_bounds__(256) void brick_rects(GeomDev G, DevGrid g, Bricks 
 }
 
 // max |proj| as the bit pattern of a non-negative float (bit order = value order).
-__global__ __launch_bounds__(256) void zero_u32(unsigned *__restrict__ p) { *p = 0u; }
+__global__ __launch_bounds__(256) void zero_u32x2(unsigned *__restrict__ p) {
+    if (threadIdx.x < 2) p[threadIdx.x] = 0u;
+}
 
 __global__ __launch_bounds__(256) void absmax_bits(const float *__restrict__ x, int64_t n,
                                                    unsigned *__restrict__ out) {
@@ -542,6 +544,171 @@ __device__ __forceinline__ double fixed_scale(const unsigned *maxbits, float sca
     return ldexp(1.0, 30 - e - headroom);
 }
 
+// ---- fixed-point mode and scale of the backprojection ------------------------
+// Two tile formats.  The 64-bit tile holds one exact sum per tile point.  The
+// packed tile holds the sums of two neighbouring points along x in the two
+// 32-bit halves of one 64-bit word, so a cell visit takes four LDS adds
+// instead of eight.  A view adds at most B * max|value| to one half, where B
+// bounds the rays through the block of eight cells around a tile point times
+// the trilinear weight one ray can give it (view_weight_bound); the scale
+// makes that at most half of the 32-bit range, and after every view each word
+// with a half beyond the other half of the range is moved into the brick's
+// 64-bit staging sums, so no half can overflow.  (The bound is far above the
+// sums of real data, so few words are moved.)  Where B is large (a unit above
+// 2^-21 of the largest value) the 64-bit tile is used.
+struct BpScale {
+    double s;         // fixed-point scale: gr = proj * length_scale * step * s
+    double inv_s;     // 1 / s
+    int packed;       // 1: packed tile (backproject_bricks<true>), 0: 64-bit tile
+    int drain_above;  // packed: a word is moved when a half exceeds this in magnitude
+};
+constexpr double kHalfCap = 2147483648.0 - 134217728.0;  // 2^31 - 2^27: the margin covers the
+                                                         // rounding of at most 2^16 flushes
+constexpr double kPackedMaxBound = 512.0;                // 2^31 / 2 * 2^-21 (one bit for the drain margin)
+
+// Upper bound, for view j, on the sum over its rays of the trilinear weight
+// that one tile point can receive.  A ray gives weight to point p only from
+// samples in the eight cells around p, a box of half-widths h inside the ball
+// of radius R = |h| about p; along a unit direction d some axis a has
+// |d_a| / h_a >= 1 / R, so consecutive samples are at least step / R apart in
+// that axis's voxel units and the ray's weights at p (bounded by the hat
+// function of that axis) sum to at most R / step + 1.  The rays through the
+// ball hit the detector inside a disk of radius rho:
+//  * parallel: rho = R / |cos| of the angle between the rays and the detector
+//    normal;
+//  * cone (and each row of a fan, within its plane): the rays through the
+//    ball lie within alpha = asin(R / dist) of the ray to its centre, and the
+//    central projection onto the plane at distance Dn moves by at most
+//    Dn / cos^2(theta) per radian at angle theta from the normal, so rho =
+//    alpha Dn / cos^2(theta_max + 2 alpha) with theta_max the largest angle of
+//    a pixel ray (a detector corner) and dist the distance from the source to
+//    the box of tile points.
+// A disk of radius rho holds at most (floor(2 rho / l) + 1) (floor(2 rho /
+// |e_v|) + 1) pixel centres, l the distance between pixel columns.  A fan's
+// rows are translates of the central row by multiples of e_v; the planes of
+// at most floor(2 R / |e_v . n0|) + 1 of them meet the ball (n0 the central
+// plane's normal).  Infinity where no bound is found.
+__device__ double view_weight_bound(const GeomDev &G, const DevGrid &g, int j) {
+    const double kInf = __longlong_as_double(0x7ff0000000000000ll);
+    const float *v = G.views + 12 * (int64_t)j;
+    double A[3], D0[3], eu[3], ev[3], h[3];
+    for (int a = 0; a < 3; ++a) {
+        A[a] = v[a];
+        D0[a] = v[3 + a];
+        eu[a] = v[6 + a];
+        ev[a] = v[9 + a];
+        h[a] = 1.0 / (double)g.inv_h[a];
+    }
+    auto dot = [](const double *x, const double *y) { return x[0] * y[0] + x[1] * y[1] + x[2] * y[2]; };
+    const double R = sqrt(dot(h, h));
+    const double W = R / G.step + 1.0;
+    const double uu = dot(eu, eu), vv = dot(ev, ev), uv = dot(eu, ev);
+    const double area2 = uu * vv - uv * uv;
+    if (!(area2 > 0.0)) return kInf;
+    const double area = sqrt(area2), lu = area / sqrt(vv);
+    const double n[3] = {(eu[1] * ev[2] - eu[2] * ev[1]) / area, (eu[2] * ev[0] - eu[0] * ev[2]) / area,
+                         (eu[0] * ev[1] - eu[1] * ev[0]) / area};
+    const double cu = 0.5 * (G.nu - 1), cv = 0.5 * (G.nv - 1);
+    const double npix = (double)G.nu * G.nv;
+    auto in_disk = [&](double rho) {
+        return fmin((floor(2.0 * rho / lu) + 1.0) * (floor(2.0 * rho / sqrt(vv)) + 1.0), npix);
+    };
+    // distance from point x to the box of tile points (voxel centres of the
+    // indices -1 ... dims: the corners of the support's cells)
+    auto box_dist = [&](const double *x) {
+        double d2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            const double b0 = (double)g.lo[a] - 0.5 * h[a];
+            const double b1 = (double)g.lo[a] + ((a == 0 ? g.nx : (a == 1 ? g.ny : g.nz)) + 0.5) * h[a];
+            const double e = x[a] < b0 ? b0 - x[a] : (x[a] > b1 ? x[a] - b1 : 0.0);
+            d2 += e * e;
+        }
+        return sqrt(d2);
+    };
+    double count;
+    if (G.kind == DGR_PARALLEL) {
+        const double c = fabs(dot(A, n)) / sqrt(dot(A, A));
+        if (!(c > 1e-6)) return kInf;
+        count = in_disk(R / c);
+    } else if (G.kind == DGR_CONE) {
+        const double w[3] = {D0[0] - A[0], D0[1] - A[1], D0[2] - A[2]};
+        const double Dn = fabs(dot(w, n));
+        const double dist = box_dist(A);
+        if (!(Dn > 0.0) || !(dist > 1.0001 * R)) return kInf;
+        const double alpha = asin(R / dist);
+        double cmin = 1.0;  // cosine of the largest pixel-ray angle
+        for (int c = 0; c < 4; ++c) {
+            const double su = (c & 1) ? cu : -cu, sv = (c & 2) ? cv : -cv;
+            double p[3];
+            for (int a = 0; a < 3; ++a) p[a] = w[a] + su * eu[a] + sv * ev[a];
+            cmin = fmin(cmin, fabs(dot(p, n)) / sqrt(dot(p, p)));
+        }
+        const double th = acos(fmin(1.0, cmin)) + 2.0 * alpha;
+        if (!(th < 1.5)) return kInf;
+        const double ct = cos(th);
+        count = in_disk(alpha * Dn / (ct * ct));
+    } else {
+        const double w[3] = {D0[0] - A[0], D0[1] - A[1], D0[2] - A[2]};
+        double n0[3] = {eu[1] * w[2] - eu[2] * w[1], eu[2] * w[0] - eu[0] * w[2], eu[0] * w[1] - eu[1] * w[0]};
+        const double nn = sqrt(dot(n0, n0));
+        if (!(nn > 0.0)) return kInf;
+        for (int a = 0; a < 3; ++a) n0[a] /= nn;
+        const double off = fabs(dot(ev, n0));
+        const double rows = off > 0.0 ? fmin(floor(2.0 * R / off) + 1.0, (double)G.nv) : (double)G.nv;
+        // in-plane normal of the detector line, and the distance to it
+        const double wu = dot(w, eu) / uu;
+        double m[3] = {w[0] - wu * eu[0], w[1] - wu * eu[1], w[2] - wu * eu[2]};
+        const double Dn = sqrt(dot(m, m));
+        // every row's source lies within cv |e_v| of the central one
+        const double dist = box_dist(A) - cv * sqrt(vv);
+        if (!(Dn > 0.0) || !(dist > 1.0001 * R)) return kInf;
+        for (int a = 0; a < 3; ++a) m[a] /= Dn;
+        const double alpha = asin(R / dist);
+        double cmin = 1.0;
+        for (int c = 0; c < 2; ++c) {
+            const double su = c ? cu : -cu;
+            double p[3];
+            for (int a = 0; a < 3; ++a) p[a] = w[a] + su * eu[a];
+            cmin = fmin(cmin, fabs(dot(p, m)) / sqrt(dot(p, p)));
+        }
+        const double th = acos(fmin(1.0, cmin)) + 2.0 * alpha;
+        if (!(th < 1.5)) return kInf;
+        const double ct = cos(th);
+        const double rho = alpha * Dn / (ct * ct);
+        count = fmin(rows * (floor(2.0 * rho / sqrt(uu)) + 1.0), npix);
+    }
+    const double B = count * W;
+    return B == B ? B : kInf;
+}
+
+// max over views of view_weight_bound, as the bit pattern of a non-negative float
+__global__ __launch_bounds__(256) void view_bound(GeomDev G, DevGrid g, unsigned *__restrict__ out) {
+    const int j = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (j >= G.n_views) return;
+    const float b = (float)fmin(view_weight_bound(G, g, j), 3.0e38);
+    atomicMax(out, __float_as_uint(b) + (b < 3.0e38f ? 1u : 0u));  // one ulp up: never below the bound
+}
+
+// Mode and scale from max |proj| and the weight bound (one thread).
+__global__ void bp_scale(const unsigned *__restrict__ words, float scale, int headroom,
+                         BpScale *__restrict__ sc) {
+    const double mc = (double)__uint_as_float(words[0]) * fabs((double)scale);
+    const double B = (double)__uint_as_float(words[1]);
+    BpScale r;
+    r.packed = B <= kPackedMaxBound ? 1 : 0;
+    r.drain_above = (int)(0.5 * kHalfCap);
+    if (!(mc > 0.0) || !(mc < 3.0e38)) {
+        r.s = 1.0;  // all values zero (or not finite)
+    } else if (r.packed) {
+        r.s = fmin(0.5 * kHalfCap / (B * mc), ldexp(1.0, 28) / mc);
+        r.drain_above = (int)floor(kHalfCap - B * mc * r.s);
+    } else {
+        r.s = fixed_scale(words, scale, headroom);
+    }
+    r.inv_s = 1.0 / r.s;
+    *sc = r;
+}
+
 // ---- per-ray table of the backprojection -------------------------------------
 // Every ray is set up once per view batch (binary64 geometry, fixed-point
 // anchor and advance, the scaled projection value) and read by each brick its
@@ -562,14 +729,10 @@ constexpr unsigned kRayMiss = 0x80000000u;
 // integer tiles.
 constexpr int64_t kRayTableBudget = int64_t(6) << 30;
 
-__global__ __launch_bounds__(256) void ray_table(const float *__restrict__ proj, GeomDev G, DevGrid g,
-                                                 int j0, int64_t nrays, const unsigned *__restrict__ maxbits,
-                                                 int headroom, RayTab *__restrict__ tab);
-
 // One thread per ray of views j0 ... (nrays rays in all).
 __global__ __launch_bounds__(256) void ray_table(const float *__restrict__ proj, GeomDev G, DevGrid g,
-                                                 int j0, int64_t nrays, const unsigned *__restrict__ maxbits,
-                                                 int headroom, RayTab *__restrict__ tab) {
+                                                 int j0, int64_t nrays, const BpScale *__restrict__ sc,
+                                                 RayTab *__restrict__ tab) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= nrays) return;
     const int64_t per_view = (int64_t)G.nu * G.nv;
@@ -577,7 +740,7 @@ __global__ __launch_bounds__(256) void ray_table(const float *__restrict__ proj,
     const int64_t pix = i - (int64_t)jl * per_view;
     const int iv = (int)(pix / G.nu), iu = (int)(pix - (int64_t)iv * G.nu);
     const int j = j0 + jl;
-    const double gs = (double)G.scale * fixed_scale(maxbits, G.scale, headroom);
+    const double gs = (double)G.scale * sc->s;
     const float gr = (float)(gs * (double)proj[(int64_t)j * per_view + pix]);
     Ray r;
     ray_geom(G, g, j, iu, iv, r);
@@ -693,10 +856,33 @@ __device__ __forceinline__ void flush_cell(unsigned long long *tile, unsigned ce
     atomicAdd(q + sz + sy + 1, h | (unsigned)(int)e[7]);
 }
 
-// Tile entry of the lower corner of in-brick cell (x, y, z): 24-bit products.
+// Packed tile: word (x, y, z), x < kBX, holds tile points (x, y, z) and
+// (x + 1, y, z) in its low and high 32 bits (two's complement halves of one
+// 64-bit sum: the low half's sign carries into the high half, and is taken
+// back out when the word is drained).
+constexpr int kPX = kBX, kPXY = kBX * kTBY, kPW3 = kBX * kTBY * kTBZ;
+
+__device__ __forceinline__ unsigned long long pack_pair(float e0, float e1) {
+    const int lo = (int)e0, hi = (int)e1;
+    return ((unsigned long long)(unsigned)(hi + (lo >> 31)) << 32) | (unsigned)lo;
+}
+
+// Adds the eight corner values of in-brick cell `word` (the word of its lower
+// corner) as four pairs along x.
+__device__ __forceinline__ void flush_packed(unsigned long long *tile, unsigned word, const float (&e)[8]) {
+    unsigned long long *q = tile + word;
+    atomicAdd(q, pack_pair(e[0], e[1]));
+    atomicAdd(q + kPX, pack_pair(e[2], e[3]));
+    atomicAdd(q + kPXY, pack_pair(e[4], e[5]));
+    atomicAdd(q + kPXY + kPX, pack_pair(e[6], e[7]));
+}
+
+// Tile entry (packed: word) of the lower corner of in-brick cell (x, y, z):
+// 24-bit products.
+template <bool PACKED>
 __device__ __forceinline__ unsigned cell_index(long long ux, long long uy, long long uz) {
-    return __umul24((unsigned)(uz >> 32), kTBX * kTBY) + __umul24((unsigned)(uy >> 32), kTBX) +
-           (unsigned)(ux >> 32);
+    constexpr unsigned sy = PACKED ? kPX : kTBX, sz = PACKED ? kPXY : kTBX * kTBY;
+    return __umul24((unsigned)(uz >> 32), sz) + (__umul24((unsigned)(uy >> 32), sy) + (unsigned)(ux >> 32));
 }
 
 // Phase 2 over the queued segments: lane i of wave w takes segments
@@ -705,6 +891,7 @@ __device__ __forceinline__ unsigned cell_index(long long ux, long long uy, long 
 // their eight corner weights in registers and adds them to the tile once per
 // cell visit.  The fixed-point scale leaves room for the largest number of
 // samples one cell can hold.
+template <bool PACKED>
 __device__ __forceinline__ void march_segments(unsigned long long *tile, const RayRec *rays,
                                                const unsigned short *segs, int nsegs, int seg_shift) {
     const int t = threadIdx.x;
@@ -738,38 +925,46 @@ __device__ __forceinline__ void march_segments(unsigned long long *tile, const R
         uy += (long long)k_off * dy;
         uz += (long long)k_off * dz;
         const float gr = rec.gr;
-        // Fixed-point conversion: every corner value of a ray has the sign of
-        // gr, so the high word of its 64-bit integer is the sign of gr.  The
-        // accumulators start at +1 or -1, so the truncated integer is at
-        // least 1 or at most -1 (never 0, whose high word would be 0 for
-        // either sign); it lies within one unit of the value, on average half
-        // a unit away from zero, with opposite signs for the two signs of gr.
+        // Fixed-point conversion (64-bit tile): every corner value of a ray
+        // has the sign of gr, so the high word of its 64-bit integer is the
+        // sign of gr.  The accumulators start at +1 or -1, so the truncated
+        // integer is at least 1 or at most -1 (never 0, whose high word would
+        // be 0 for either sign); it lies within one unit of the value, on
+        // average half a unit away from zero, with opposite signs for the two
+        // signs of gr.  Packed tile: the accumulators start at +-1/2, so the
+        // truncation rounds to the nearest integer (each half carries its own
+        // sign).
         const float gr32 = gr * kInv32;  // exact: a power-of-two scale
         const unsigned hi = gr < 0.0f ? 0xffffffffu : 0u;
-        const float a_init = gr < 0.0f ? -1.0f : 1.0f;
-        unsigned cell = cell_index(ux, uy, uz);
+        const float a_init = PACKED ? (gr < 0.0f ? -0.5f : 0.5f) : (gr < 0.0f ? -1.0f : 1.0f);
+        unsigned cell = cell_index<PACKED>(ux, uy, uz);
         float acc[8] = {a_init, a_init, a_init, a_init, a_init, a_init, a_init, a_init};
         for (int i = 0; i < cnt; ++i) {
-            const unsigned here = cell_index(ux, uy, uz);
+            const unsigned here = cell_index<PACKED>(ux, uy, uz);
             // 2^32 times the trilinear weights of the upper corners
             const float fx = (float)(unsigned)ux, fy = (float)(unsigned)uy, fz = (float)(unsigned)uz;
             ux += dx;
             uy += dy;
             uz += dz;
             if (here != cell) {
-                flush_cell(tile, cell, acc, hi);
+                if (PACKED)
+                    flush_packed(tile, cell, acc);
+                else
+                    flush_cell(tile, cell, acc, hi);
 #pragma unroll
                 for (int c = 0; c < 8; ++c) acc[c] = a_init;
                 cell = here;
             }
-            // Every corner value is a product of gr and non-negative factors,
-            // added with an explicit fma, so it has the sign of gr whatever
-            // the compiler contracts (a difference such as z1 - z1 * wy, fused
-            // with an unrounded product, could flip the sign of a rounding
-            // residue and break the high word above).
-            const float z1 = gr32 * fz, z0 = gr * fmaf(-fz, kInv32, 1.0f);
-            const float wy = fy * kInv32, oy = fmaf(-fy, kInv32, 1.0f);
-            const float y00 = z0 * oy, y01 = z0 * wy, y10 = z1 * oy, y11 = z1 * wy;
+            // Every corner value has the sign of gr (or is 0), so the high
+            // word above holds: z1 = gr 2^-32 fz with fz <= 2^32 is at most gr
+            // in magnitude, and each lower-corner factor is formed as
+            // fma(-z, w, z) = z (1 - w), rounded once from the exact value,
+            // with 0 <= w <= 1.  (Where gr 2^-32 is subnormal a residue of the
+            // wrong sign below 2^-94 is possible; added to an accumulator of
+            // magnitude >= 1 it rounds away.)
+            const float z1 = gr32 * fz, z0 = fmaf(-gr32, fz, gr);
+            const float wy = fy * kInv32;
+            const float y01 = z0 * wy, y11 = z1 * wy, y00 = fmaf(-z0, wy, z0), y10 = fmaf(-z1, wy, z1);
             const float wx = fx * kInv32, ox = fmaf(-fx, kInv32, 1.0f);
             acc[0] = fmaf(y00, ox, acc[0]);
             acc[1] = fmaf(y00, wx, acc[1]);
@@ -780,21 +975,32 @@ __device__ __forceinline__ void march_segments(unsigned long long *tile, const R
             acc[6] = fmaf(y11, ox, acc[6]);
             acc[7] = fmaf(y11, wx, acc[7]);
         }
-        flush_cell(tile, cell, acc, hi);
+        if (PACKED)
+            flush_packed(tile, cell, acc);
+        else
+            flush_cell(tile, cell, acc, hi);
     }
 }
 
 // seg_shift: log2 of the samples per segment, chosen on the host so that no ray
 // in a brick has more than kMaxSeg segments (and no more than 256 samples).
 // Four work-groups per CU (37 KB of LDS each, <= 128 VGPRs): the extra waves
-// overlap one work-group's LDS adds with another's arithmetic.
+// overlap one work-group's LDS adds with another's arithmetic.  Both
+// instances are launched; the one whose tile format sc->packed does not name
+// returns at once.  The 64-bit tile is written to (accumulate: loaded from
+// and written to) the brick's staging sums at the end; the packed tile's
+// words are added into them when a half nears the end of its range (checked
+// after every view) and at the end.
+template <bool PACKED>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DGR_BP_WAVES, DGR_BP_WAVES))) void backproject_bricks(
     const RayTab *__restrict__ tab, int j0, int nj, GeomDev G, Bricks bk, const ushort4 *__restrict__ rect,
-    int seg_shift, int accumulate, long long *__restrict__ staging) {
-    __shared__ unsigned long long tile[kBT3];
+    int seg_shift, int accumulate, const BpScale *__restrict__ sc, long long *__restrict__ staging) {
+    constexpr int kTile = PACKED ? kPW3 : kBT3;
+    __shared__ unsigned long long tile[kTile];
     __shared__ RayRec rays[kRayCap];
     __shared__ unsigned short segs[kSegCap];
     __shared__ int q_rays, q_segs;
+    if (sc->packed != (PACKED ? 1 : 0)) return;
     const int t = threadIdx.x, lane = t & 63;
     const int64_t nb = bk.count();
     const int64_t b = blockIdx.x;
@@ -812,7 +1018,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DGR_BP_WAVE
                               C0z + ((long long)kBZ << 32)};
     const int64_t per_view = (int64_t)G.nu * G.nv;
     long long *out = staging + b * kBT3;
-    for (int e = t; e < kBT3; e += 256) tile[e] = accumulate ? (unsigned long long)out[e] : 0ull;
+    if (PACKED) {
+        for (int e = t; e < kTile; e += 256) tile[e] = 0ull;
+        // the staging sums start at zero; the barriers of the loop (which
+        // wait for these stores) precede the first drain's atomics
+        if (!accumulate)
+            for (int e = t; e < kBT3; e += 256) out[e] = 0;
+    } else {
+        for (int e = t; e < kBT3; e += 256) tile[e] = accumulate ? (unsigned long long)out[e] : 0ull;
+    }
+    // packed: moves the two halves of a word into the staging sums of its two
+    // tile points with non-returning 64-bit atomics (the brick's sums are its
+    // own, so the atomics meet no other work-group; they only spare the wait
+    // of a read-modify-write) and clears the word: every word (all) or those
+    // with a half beyond drain_above
+    const int drain_above = PACKED ? sc->drain_above : 0;
+    auto drain = [&](bool all) {
+        for (int w = t; w < kPW3; w += 256) {
+            const unsigned long long p = tile[w];
+            const int lo = (int)(unsigned)p;
+            const int hi = (int)((long long)(p - (unsigned long long)(long long)lo) >> 32);
+            if (all ? p != 0ull : (abs(lo) > drain_above || abs(hi) > drain_above)) {
+                tile[w] = 0ull;
+                const int z = w / kPXY, r = w - z * kPXY;
+                const int y = r / kPX, x = r - y * kPX;
+                unsigned long long *q = reinterpret_cast<unsigned long long *>(out + (z * kTBY + y) * kTBX + x);
+                if (lo != 0) atomicAdd(q, (unsigned long long)(long long)lo);
+                if (hi != 0) atomicAdd(q + 1, (unsigned long long)(long long)hi);
+            }
+        }
+    };
     if (t == 0) {
         q_rays = 0;
         q_segs = 0;
@@ -933,7 +1168,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DGR_BP_WAVE
         const int ns = q_segs;
         // ---- phase 2; then each wave sets up its rays of the next chunk
         // while the other waves finish their segments
-        march_segments(tile, rays, segs, ns, seg_shift);
+        march_segments<PACKED>(tile, rays, segs, ns, seg_shift);
+        const int j_marched = j;
         advance();
         n = 0;
         if (j < jend && cb + t < ncand) n = setup(j, rc, inu, cb + t, rec);
@@ -942,18 +1178,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DGR_BP_WAVE
             q_rays = 0;
             q_segs = 0;
         }
+        if (PACKED && j != j_marched && j < jend) drain(false);  // view j_marched is complete
+                                                                   // (the last drain follows the loop)
         __syncthreads();
     }
-    for (int e = t; e < kBT3; e += 256) out[e] = (long long)tile[e];
+    if (PACKED) {
+        drain(true);
+    } else {
+        for (int e = t; e < kBT3; e += 256) out[e] = (long long)tile[e];
+    }
 }
 
 // Each voxel lies in one or two brick tiles per axis (tiles overlap by one
 // voxel on their faces); its value is the exact integer sum of those tile
 // entries divided by the fixed-point scale.
 __global__ __launch_bounds__(256) void gather_bricks(const long long *__restrict__ staging, DevGrid g,
-                                                     Bricks bk, const unsigned *__restrict__ maxbits,
-                                                     float scale, int headroom, float *__restrict__ V) {
-    const double inv_s = 1.0 / fixed_scale(maxbits, scale, headroom);
+                                                     Bricks bk, const BpScale *__restrict__ sc,
+                                                     float *__restrict__ V) {
+    const double inv_s = sc->inv_s;
     const int64_t total = (int64_t)g.nx * g.ny * g.nz;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
         const int64_t z = i / ((int64_t)g.nx * g.ny), rem = i - z * (int64_t)g.nx * g.ny;
@@ -989,7 +1231,8 @@ struct ProjWs {
     float *partial;
     long long *staging;
     ushort4 *rect;
-    unsigned *maxbits;
+    unsigned *maxbits;  // [0]: max |proj| (float bits), [1]: view weight bound (float bits)
+    BpScale *scale;
     RayTab *tab;
     int batch_views;  // views per backprojection batch (ray table rows: batch_views * nu * nv)
     size_t bytes;
@@ -1013,7 +1256,8 @@ ProjWs carve_proj_ws(void *ws, const dgr_grid *grid, const dgr_geometry *geom) {
     const Bricks bk = bricks_of(grid);
     w.staging = b.take<long long>(bk.count() * kBT3);
     w.rect = b.take<ushort4>(bk.count() * geom->n_views);
-    w.maxbits = b.take<unsigned>(1);
+    w.maxbits = b.take<unsigned>(2);
+    w.scale = b.take<BpScale>(1);
     const int64_t row_bytes = (int64_t)geom->nu * geom->nv * (int64_t)sizeof(RayTab);
     const int64_t fit = std::max<int64_t>(1, kRayTableBudget / std::max<int64_t>(row_bytes, 1));
     const int64_t nbatch = (geom->n_views + fit - 1) / fit;  // equal batches
@@ -1148,27 +1392,33 @@ extern "C" dgr_status dgr_backproject(const float *proj, const dgr_grid *grid,
     brick_rects<<<dim3((unsigned)((nrect + 255) / 256)), dim3(256), 0, st>>>(G, g, bk, w.rect);
     DGR_LAUNCH_CHECK();
     const int64_t nproj = (int64_t)geom->n_views * geom->nu * geom->nv;
-    zero_u32<<<1, 1, 0, st>>>(w.maxbits);
+    zero_u32x2<<<1, 64, 0, st>>>(w.maxbits);
     DGR_LAUNCH_CHECK();
     absmax_bits<<<dim3((unsigned)std::min<int64_t>((nproj / 4 + 255) / 256 + 1, 2048)), dim3(256), 0, st>>>(
         proj, nproj, w.maxbits);
+    DGR_LAUNCH_CHECK();
+    view_bound<<<dim3((unsigned)((geom->n_views + 255) / 256)), dim3(256), 0, st>>>(G, g, w.maxbits + 1);
+    DGR_LAUNCH_CHECK();
+    bp_scale<<<1, 1, 0, st>>>(w.maxbits, G.scale, headroom, w.scale);
     DGR_LAUNCH_CHECK();
     // views in batches whose ray table fits the budget; each batch adds into
     // the integer tiles of the previous ones
     for (int j0 = 0; j0 < geom->n_views; j0 += w.batch_views) {
         const int nj = std::min(w.batch_views, geom->n_views - j0);
         const int64_t nrays = (int64_t)nj * geom->nu * geom->nv;
-        ray_table<<<dim3((unsigned)((nrays + 255) / 256)), dim3(256), 0, st>>>(proj, G, g, j0, nrays, w.maxbits,
-                                                                              headroom, w.tab);
+        ray_table<<<dim3((unsigned)((nrays + 255) / 256)), dim3(256), 0, st>>>(proj, G, g, j0, nrays, w.scale,
+                                                                              w.tab);
         DGR_LAUNCH_CHECK();
-        backproject_bricks<<<dim3((unsigned)bk.count()), dim3(256), 0, st>>>(w.tab, j0, nj, G, bk, w.rect,
-                                                                             seg_shift, j0 > 0 ? 1 : 0,
-                                                                             w.staging);
+        // the instance whose tile format the scale kernel did not choose returns at once
+        backproject_bricks<true><<<dim3((unsigned)bk.count()), dim3(256), 0, st>>>(
+            w.tab, j0, nj, G, bk, w.rect, seg_shift, j0 > 0 ? 1 : 0, w.scale, w.staging);
+        DGR_LAUNCH_CHECK();
+        backproject_bricks<false><<<dim3((unsigned)bk.count()), dim3(256), 0, st>>>(
+            w.tab, j0, nj, G, bk, w.rect, seg_shift, j0 > 0 ? 1 : 0, w.scale, w.staging);
         DGR_LAUNCH_CHECK();
     }
     const int64_t nvox = (int64_t)grid->dims[0] * grid->dims[1] * grid->dims[2];
-    gather_bricks<<<dim3(grid_stride_blocks(nvox)), dim3(256), 0, st>>>(w.staging, g, bk, w.maxbits,
-                                                                        G.scale, headroom, volume);
+    gather_bricks<<<dim3(grid_stride_blocks(nvox)), dim3(256), 0, st>>>(w.staging, g, bk, w.scale, volume);
     DGR_LAUNCH_CHECK();
     return DGR_OK;
 }

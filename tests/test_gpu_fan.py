@@ -224,7 +224,9 @@ def test_fan_sparse_view_and_limited_angle_loops_reconstruct():
 
 def test_fan_single_row_equals_cone_central_row():
     """One detector row: the fan-beam row's source is the cone source, so the
-    two projections (and backprojections) are the same numbers."""
+    two projections are the same numbers, and so are the two backprojections
+    up to their fixed-point rounding (the fixed-point scale follows a weight
+    bound that each geometry computes in its own way)."""
     say("fan single row")
     fan = inputs.fan_geometry(7, 33, 1, 0.05, 1.0 / 24, 7.8125, 11.71875, 1.0 / 48)
     cone = inputs.cone_geometry(7, 33, 1, 0.05, 7.8125, 11.71875, 1.0 / 48)
@@ -235,4 +237,5 @@ def test_fan_single_row_equals_cone_central_row():
     g = dev(np.random.default_rng(306).normal(size=a.shape).astype(np.float32))
     A = native.dgr_backproject(g, GRID, fan, dev(fan.views)).cpu().numpy()
     B = native.dgr_backproject(g, GRID, cone, dev(cone.views)).cpu().numpy()
-    assert np.array_equal(A, B)
+    assert np.count_nonzero(B) > 0.005 * B.size
+    assert rel_l2(A, B) < 1e-6 and np.abs(A - B).max() < 1e-6 * np.abs(B).max()

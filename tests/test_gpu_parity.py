@@ -182,7 +182,17 @@ def _geoms():
     grid_p = inputs.cube_grid(64)
     grid_c = inputs.GridSpec((48, 44, 40), (-1.0, -1.0 * 44 / 48, -1.0 * 40 / 48), (24.0, 24.0, 24.0))
     cone = inputs.cone_geometry(10, 70, 45, 0.02, 7.8125, 11.71875, 1.0 / 48, arc=2 * math.pi)
-    return {"parallel": (grid_p, small_parallel_geometry()), "cone": (grid_c, cone)}
+    cone_coarse = inputs.cone_geometry(10, 40, 30, 0.04, 7.8125, 11.71875, 1.0 / 48, arc=2 * math.pi)
+    return {"parallel": (grid_p, small_parallel_geometry()), "cone": (grid_c, cone),
+            "cone_coarse": (grid_c, cone_coarse)}
+
+
+# Tile format of the brickwise backprojection per geometry: the per-view weight
+# bound (rays through the eight cells around a tile point times one ray's
+# largest weight sum there) is about 71 for "parallel" and 219 for
+# "cone_coarse" (packed 32-bit halves), 875 for "cone" (pixels twice as fine:
+# the exact 64-bit tile; the packed format needs a bound of at most 512).
+BACKPROJECT_KINDS = ["parallel", "cone", "cone_coarse"]
 
 
 @pytest.mark.parametrize("kind", ["parallel", "cone"])
@@ -224,7 +234,7 @@ def test_project_l1_parity(kind):
     assert mism.mean() < 2e-3
 
 
-@pytest.mark.parametrize("kind", ["parallel", "cone"])
+@pytest.mark.parametrize("kind", BACKPROJECT_KINDS)
 def test_backproject_parity_and_adjoint(kind):
     grid, geom = _geoms()[kind]
     say("backproject", kind)
@@ -264,12 +274,14 @@ def test_backproject_brick_rectangle_beyond_2_22_candidates():
     assert err < TOL and worst < 1e-5
 
 
-def test_backproject_tiny_and_huge_values():
-    """The fixed-point scale is a power of two chosen from max |g| and ranges
-    beyond binary32 (2^-128 ... 2^180): data scaled by 2^-120 or 2^100
-    backprojects to the same numbers scaled alike, and matches the oracle."""
-    grid, geom = _geoms()["cone"]
-    say("backproject tiny and huge values")
+@pytest.mark.parametrize("kind", ["cone", "cone_coarse"])
+def test_backproject_tiny_and_huge_values(kind):
+    """The fixed-point scale follows max |g| and ranges beyond binary32
+    (2^-128 ... 2^180): data scaled by 2^-120 or 2^100 backprojects to the
+    same numbers scaled alike, and matches the oracle (64-bit tile: a power of
+    two; packed tile: the weight bound's quotient)."""
+    grid, geom = _geoms()[kind]
+    say("backproject tiny and huge values", kind)
     g = np.random.default_rng(96).normal(size=(geom.n_views, geom.nv, geom.nu)).astype(np.float32)
     views = dev(geom.views)
     base = native.dgr_backproject(dev(g), grid, geom, views).cpu().numpy().astype(np.float64)
@@ -282,6 +294,23 @@ def test_backproject_tiny_and_huge_values():
         assert np.all(np.isfinite(got)) and np.abs(got).max() > 0
         assert rel_l2(got, want) < TOL
         assert rel_l2(got * 2.0 ** -e, base) < 1e-6
+
+
+@pytest.mark.parametrize("kind", BACKPROJECT_KINDS)
+def test_backproject_constant_data(kind):
+    """g = 1 on every pixel: every tile point receives its largest possible
+    sum (all values of one sign at the largest magnitude), the case that
+    presses the packed tile's 32-bit halves hardest; the result still matches
+    the oracle voxel by voxel."""
+    grid, geom = _geoms()[kind]
+    say("backproject constant data", kind)
+    g = np.ones((geom.n_views, geom.nv, geom.nu), np.float32)
+    got = native.dgr_backproject(dev(g), grid, geom, dev(geom.views)).cpu().numpy()
+    want = oracle.backproject(g.astype(np.float64), grid.dims, grid.lo, grid.inv_h, geom.kind, geom.views,
+                              geom.nu, geom.nv, geom.step, geom.length_scale)
+    worst = float(np.abs(got.astype(np.float64) - want).max() / np.abs(want).max())
+    say("backproject constant data", kind, "rel_l2", rel_l2(got, want), "worst voxel / max", worst)
+    assert rel_l2(got, want) < TOL and worst < 1e-5
 
 
 def test_project_rays_with_disjoint_sample_ranges():
