@@ -68,9 +68,9 @@ def count_samples(prob) -> int:
 
 REPO = os.path.dirname(os.path.abspath(__file__))
 COUNTER_FILE = os.path.join(REPO, "profiles", "counters_cone256.txt")
-KERNEL_SOURCE = {"backproject": "backproject_bricks", "project_l1": "project_bundles<1>"}
+KERNEL_SOURCE = {"backproject": "backproject_bricks<true>", "project_l1": "project_bundles<1>"}
 # the source file each profiled kernel is built from (with internal.h)
-KERNEL_FILE = {"backproject_bricks": "project.hip", "project_bundles<1>": "project.hip",
+KERNEL_FILE = {"backproject_bricks<true>": "project.hip", "project_bundles<1>": "project.hip",
                "voxelize_tiles": "voxelize.hip", "voxelize_grad": "voxelize_bwd.hip",
                "ssim_fwd": "objective.hip", "ssim_bwd": "objective.hip", "tv_kernel": "objective.hip",
                "adam_kernel": "adam.hip"}

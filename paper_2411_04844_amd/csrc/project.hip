@@ -799,9 +799,10 @@ __device__ bool k_interval_fixed(const long long U[3], const long long DU[3], co
 //     lane runs (nearly) the same number of samples whatever the chord lengths
 //     of the rays, and add the eight weighted values of each sample, in fixed
 //     point, into the LDS tile.
-// The queue holds one chunk of 256 candidates and is drained after it; each
-// wave sets up its rays of the next chunk as soon as its part of the drain is
-// done, while the other waves still march.
+// The queue holds one chunk of 256 candidates and is emptied by the march;
+// each wave's table rows for the next chunk are in flight during its part of
+// the march, and it sets those rays up as soon as that part is done, while
+// the other waves still march.
 constexpr int kChunk = 256;     // candidates per set-up pass (one per thread)
 constexpr int kRayCap = 256;    // queued rays (one chunk)
 constexpr int kSegCap = 2048;   // queued segments (>= kChunk * kMaxSeg)
@@ -1053,12 +1054,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DGR_BP_WAVE
         q_segs = 0;
     }
     __syncthreads();
-    // Ray set-up (phase 1) of candidate c of view j's rectangle rc, from the
-    // ray's table row: the record and the number of the ray's samples in the
-    // brick (0: none).
-    auto setup = [&](int j, const ushort4 &rc, float inu, long long c, RayRec &rec) -> int {
+    // Ray set-up (phase 1), in two parts: the table row of candidate c of view
+    // j's rectangle rc, and from that row the record and the number of the
+    // ray's samples in the brick (0: none).
+    auto row_of = [&](int j, const ushort4 &rc, float inu, long long c) -> int64_t {
         const int nu_r = (int)rc.y - (int)rc.x + 1;
-        int n = 0;
         // c / nu_r from a binary32 reciprocal, exact for c < 2^22 (as in the
         // forward staging); integer division beyond
         int row, col;
@@ -1070,7 +1070,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DGR_BP_WAVE
             col = (int)(c - (long long)row * nu_r);
         }
         const int iv = (int)rc.z + row, iu = (int)rc.x + col;
-        const RayTab rt = tab[(int64_t)(j - j0) * per_view + (int64_t)iv * G.nu + iu];
+        return (int64_t)(j - j0) * per_view + (int64_t)iv * G.nu + iu;
+    };
+    auto finish = [&](const RayTab &rt, RayRec &rec) -> int {
+        int n = 0;
         if (rt.meta & kRayMiss) return 0;
         long long DU[3];
 #pragma unroll
@@ -1143,7 +1146,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DGR_BP_WAVE
     RayRec rec;
     int n = 0;
     advance();
-    if (j < jend && cb + t < ncand) n = setup(j, rc, inu, cb + t, rec);
+    if (j < jend && cb + t < ncand) n = finish(tab[row_of(j, rc, inu, cb + t)], rec);
     while (j < jend) {
         // ---- queue the chunk's rays and segments (the queue is empty)
         const int nseg = (n + (1 << seg_shift) - 1) >> seg_shift;
@@ -1166,13 +1169,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DGR_BP_WAVE
         }
         __syncthreads();
         const int ns = q_segs;
-        // ---- phase 2; then each wave sets up its rays of the next chunk
-        // while the other waves finish their segments
-        march_segments<PACKED>(tile, rays, segs, ns, seg_shift);
+        // ---- phase 2; each wave loads the table rows of its candidates of
+        // the next chunk before its part of the march and sets them up after
+        // it, while the other waves finish their segments
         const int j_marched = j;
         advance();
-        n = 0;
-        if (j < jend && cb + t < ncand) n = setup(j, rc, inu, cb + t, rec);
+        const bool have = j < jend && cb + t < ncand;
+        // (unconditional load, row 0 for lanes without a candidate: no
+        // branch, so nothing waits for the load before the march)
+        const RayTab rt_next = tab[have ? row_of(j, rc, inu, cb + t) : 0];
+        march_segments<PACKED>(tile, rays, segs, ns, seg_shift);
+        n = have ? finish(rt_next, rec) : 0;
         __syncthreads();
         if (t == 0) {
             q_rays = 0;
