@@ -70,6 +70,10 @@ REPO = os.path.dirname(os.path.abspath(__file__))
 COUNTER_FILE = os.path.join(REPO, "profiles", "counters_cone256.txt")
 KERNEL_SOURCE = {"backproject": "backproject_bricks<true>", "project_l1": "project_bundles<1>"}
 # the source file each profiled kernel is built from (with internal.h)
+# kernels (and launches per stage) of the HBM-stage lines
+STAGE_KERNELS = {"voxelize": [("voxelize_tiles", 1)], "voxelize_backward": [("voxelize_grad", 1)],
+                 "adam": [("adam_kernel", 4)], "projection_loss": [("ssim_fwd", 1), ("ssim_bwd", 1)],
+                 "tv": [("tv_kernel", 1)]}
 KERNEL_FILE = {"backproject_bricks<true>": "project.hip", "project_bundles<1>": "project.hip",
                "voxelize_tiles": "voxelize.hip", "voxelize_grad": "voxelize_bwd.hip",
                "ssim_fwd": "objective.hip", "ssim_bwd": "objective.hip", "tv_kernel": "objective.hip",
@@ -464,6 +468,17 @@ def main():
         hbm[k] = {"bytes": b, "ms": t, "GB/s": round(b / (t * 1e-3) / 1e9, 1),
                   "frac": round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     del itf
+    # the same stages against the VALU issue rate (committed counters of
+    # their kernels, while the sources are unchanged): the voxelization pair
+    # is bound by its exp2 evaluations, not by HBM
+    for k, kernels in STAGE_KERNELS.items():
+        rows = [(committed_counters(kn), calls) for kn, calls in kernels]
+        if k not in hbm or any(c is None for c, _ in rows):
+            continue
+        lane = sum(c["valu"] * calls for c, calls in rows) * 64.0
+        rate = lane / (hbm[k]["ms"] * 1e-3)
+        hbm[k]["valu_issue_frac"] = round(rate / VALU_LANE_INSTR_PER_S, 4)
+        hbm[k]["bound"] = "alu" if hbm[k]["valu_issue_frac"] > hbm[k]["frac"] else "hbm"
     log("fixed-box voxelization sweep")
     fvr = fvr_leg()
     rec = None
