@@ -183,16 +183,23 @@ def _geoms():
     grid_c = inputs.GridSpec((48, 44, 40), (-1.0, -1.0 * 44 / 48, -1.0 * 40 / 48), (24.0, 24.0, 24.0))
     cone = inputs.cone_geometry(10, 70, 45, 0.02, 7.8125, 11.71875, 1.0 / 48, arc=2 * math.pi)
     cone_coarse = inputs.cone_geometry(10, 40, 30, 0.04, 7.8125, 11.71875, 1.0 / 48, arc=2 * math.pi)
+    # parallel rays 35 degrees out of the detector's normal (a tilted beam)
+    par = small_parallel_geometry()
+    v = par.views.astype(np.float64).copy()
+    b = math.radians(35.0)
+    v[:, 0:3] = np.stack([v[:, 0] * math.cos(b), v[:, 1] * math.cos(b), np.full(len(v), math.sin(b))], axis=1)
+    oblique = inputs.Geometry(0, v.astype(np.float32), par.nu, par.nv, par.step, par.length_scale)
     return {"parallel": (grid_p, small_parallel_geometry()), "cone": (grid_c, cone),
-            "cone_coarse": (grid_c, cone_coarse)}
+            "cone_coarse": (grid_c, cone_coarse), "parallel_oblique": (grid_p, oblique)}
 
 
 # Tile format of the brickwise backprojection per geometry: the per-view weight
 # bound (rays through the eight cells around a tile point times one ray's
-# largest weight sum there) is about 71 for "parallel" and 219 for
+# largest weight sum there) is about 71 for "parallel", 112 for
+# "parallel_oblique" (the rays' 1/cos widens their footprint) and 219 for
 # "cone_coarse" (packed 32-bit halves), 875 for "cone" (pixels twice as fine:
 # the exact 64-bit tile; the packed format needs a bound of at most 512).
-BACKPROJECT_KINDS = ["parallel", "cone", "cone_coarse"]
+BACKPROJECT_KINDS = ["parallel", "parallel_oblique", "cone", "cone_coarse"]
 
 
 @pytest.mark.parametrize("kind", ["parallel", "cone"])
