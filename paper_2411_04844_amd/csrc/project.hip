@@ -1021,8 +1021,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DGR_BP_WAVE
     long long *out = staging + b * kBT3;
     if (PACKED) {
         for (int e = t; e < kTile; e += 256) tile[e] = 0ull;
-        // the staging sums start at zero; the barriers of the loop (which
-        // wait for these stores) precede the first drain's atomics
+        // the staging sums start at zero; the loop's barriers (work-group
+        // release and acquire) order these stores before every drain's
+        // atomics on the same words, which this work-group alone touches
         if (!accumulate)
             for (int e = t; e < kBT3; e += 256) out[e] = 0;
     } else {
