@@ -192,13 +192,17 @@ dgr_status dgr_project_l1(const float *volume, const dgr_grid *grid, const dgr_g
                           size_t ws_bytes, void *stream);
 
 /* volume [nz][ny][nx] = T^T(proj): the exact transpose of dgr_project.
- * Deterministic: the per-voxel sums are 64-bit fixed point (a power-of-two
- * scale from max|proj|; each sum of one ray's samples in one cell is rounded
- * to within one unit, about 2^-27 max|proj| length_scale step at half-voxel
- * steps), so they do not depend on the order of the adds.  The march step,
- * in voxels of every axis, must lie between 0.12 and 3.9 (at most 256
- * samples of one ray in a brick of 20 x 20 x 10 voxels, advances below 4
- * voxels); DGR_ERR_INVALID_ARG otherwise. */
+ * Deterministic: the per-voxel sums are 64-bit fixed-point integers, so they
+ * do not depend on the order of the adds.  The fixed-point unit follows
+ * max|proj| and the geometry: where a per-view bound on the weight one voxel
+ * can receive (computed on the device from the view vectors) allows it, two
+ * voxels share one 64-bit LDS word as 32-bit halves and each sum of one
+ * ray's samples in one cell is rounded to the nearest unit, at most 2^-21
+ * of max|proj| length_scale step (2^-22.5 for the 256^3 / 512^2 cone scan);
+ * otherwise one voxel per word with a power-of-two unit of about 2^-27 of
+ * it, truncated.  The march step, in voxels of every axis, must lie between
+ * 0.12 and 3.9 (at most 256 samples of one ray in a brick of 20 x 20 x 6
+ * voxels, advances below 4 voxels); DGR_ERR_INVALID_ARG otherwise. */
 dgr_status dgr_backproject(const float *proj, const dgr_grid *grid, const dgr_geometry *geom,
                            float *volume, void *ws, size_t ws_bytes, void *stream);
 
