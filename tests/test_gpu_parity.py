@@ -320,6 +320,17 @@ def test_backproject_constant_data(kind):
     assert rel_l2(got, want) < TOL and worst < 1e-5
 
 
+@pytest.mark.parametrize("kind", ["cone", "cone_coarse"])
+def test_backproject_zero_data(kind):
+    """All-zero data (max |g| = 0: no fixed-point scale can be formed; every
+    ray is skipped) backprojects to exact zeros on both tile formats."""
+    grid, geom = _geoms()[kind]
+    say("backproject zero data", kind)
+    g = np.zeros((geom.n_views, geom.nv, geom.nu), np.float32)
+    out = native.dgr_backproject(dev(g), grid, geom, dev(geom.views))
+    assert not bool(torch.any(out != 0.0))
+
+
 def test_project_rays_with_disjoint_sample_ranges():
     """Two rays of one pixel bundle whose sample ranges are far apart
     ([-149, -50] and [50, 149]): the chunks between them hold no sample of
