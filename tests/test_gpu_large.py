@@ -78,3 +78,27 @@ def test_large_volume_gradient_vs_finite_differences():
     assert ratio[gids[:32]].max() > 8.0  # the 10:1 end of the range is covered
     assert np.quantile(err, 0.9) < 1e-4
     assert err.max() < 1e-3
+
+
+def test_large_backproject_across_view_batches():
+    """720 views of 1024^2 need six batches of the ray table (6 GiB each at
+    most): data on two views of different batches backprojects, through the
+    packed tile whose sums each batch adds to the previous batches', to the
+    oracle's volume voxel by voxel.  (Two views of random data and two of
+    constant data, so both the rounding and the largest sums are tested.)"""
+    import oracle
+    grid = inputs.cube_grid(512)
+    geom = inputs.cone_workload(512, 720, 1024, 0.4)
+    views = torch.as_tensor(geom.views).cuda()
+    rng = np.random.default_rng(4005)
+    for name, sel in (("random", [7, 371]), ("constant", [250, 611])):
+        say("large backproject across batches", name, sel)
+        g = np.zeros((geom.n_views, geom.nv, geom.nu), np.float32)
+        g[sel] = rng.normal(size=(len(sel), geom.nv, geom.nu)) if name == "random" else 1.0
+        got = native.dgr_backproject(torch.as_tensor(g).cuda(), grid, geom, views).cpu().numpy()
+        want = oracle.backproject(g[sel].astype(np.float64), grid.dims, grid.lo, grid.inv_h, geom.kind,
+                                  geom.views[sel], geom.nu, geom.nv, geom.step, geom.length_scale)
+        err = float(np.linalg.norm(got.astype(np.float64) - want) / np.linalg.norm(want))
+        worst = float(np.abs(got.astype(np.float64) - want).max() / np.abs(want).max())
+        say("large backproject", name, "rel_l2", err, "worst voxel / max", worst)
+        assert err < 1e-5 and worst < 1e-5
