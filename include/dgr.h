@@ -203,6 +203,16 @@ dgr_status dgr_project_l1(const float *volume, const dgr_grid *grid, const dgr_g
  * it, truncated.  The march step, in voxels of every axis, must lie between
  * 0.12 and 3.9 (at most 256 samples of one ray in a brick of 20 x 20 x 6
  * voxels, advances below 4 voxels); DGR_ERR_INVALID_ARG otherwise. */
+/* bound[n_views] (DEVICE, binary32): for each view, the bound that
+ * dgr_backproject uses for the weight one voxel can receive from that view's
+ * rays (the rays through the eight cells around the voxel times the largest
+ * weight sum one ray can give it, rounded up), in units of one projection
+ * value times length_scale * step; 3e38 where no bound is found.  The
+ * largest over the views picks the fixed-point tile (packed when at most
+ * 512).  Asynchronous; for inspection and tests. */
+dgr_status dgr_backproject_weight_bound(const dgr_grid *grid, const dgr_geometry *geom, float *bound,
+                                        void *stream);
+
 dgr_status dgr_backproject(const float *proj, const dgr_grid *grid, const dgr_geometry *geom,
                            float *volume, void *ws, size_t ws_bytes, void *stream);
 

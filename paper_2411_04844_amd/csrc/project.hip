@@ -681,12 +681,17 @@ __device__ double view_weight_bound(const GeomDev &G, const DevGrid &g, int j) {
     return B == B ? B : kInf;
 }
 
-// max over views of view_weight_bound, as the bit pattern of a non-negative float
-__global__ __launch_bounds__(256) void view_bound(GeomDev G, DevGrid g, unsigned *__restrict__ out) {
+// max over views of view_weight_bound, as the bit pattern of a non-negative
+// float (out), and each view's bound (per_view, if not null; 3e38 where
+// none is found)
+__global__ __launch_bounds__(256) void view_bound(GeomDev G, DevGrid g, unsigned *__restrict__ out,
+                                                  float *__restrict__ per_view) {
     const int j = (int)(blockIdx.x * 256 + threadIdx.x);
     if (j >= G.n_views) return;
     const float b = (float)fmin(view_weight_bound(G, g, j), 3.0e38);
-    atomicMax(out, __float_as_uint(b) + (b < 3.0e38f ? 1u : 0u));  // one ulp up: never below the bound
+    const unsigned bits = __float_as_uint(b) + (b < 3.0e38f ? 1u : 0u);  // one ulp up: never below the bound
+    if (out) atomicMax(out, bits);
+    if (per_view) per_view[j] = __uint_as_float(bits);
 }
 
 // Mode and scale from max |proj| and the weight bound (one thread).
@@ -1365,6 +1370,18 @@ extern "C" dgr_status dgr_project_l1(const float *volume, const dgr_grid *grid,
     return project_impl<1>(volume, grid, geom, target, loss, dproj, ws, ws_bytes, stream);
 }
 
+extern "C" dgr_status dgr_backproject_weight_bound(const dgr_grid *grid, const dgr_geometry *geom,
+                                                   float *bound, void *stream) {
+    dgr_status s;
+    if ((s = check_grid(grid)) != DGR_OK) return s;
+    if ((s = check_geometry(geom)) != DGR_OK) return s;
+    DGR_CHECK(bound, "null bound pointer");
+    view_bound<<<dim3((unsigned)((geom->n_views + 255) / 256)), dim3(256), 0, as_stream(stream)>>>(
+        geom_dev(geom), dev_grid(grid), nullptr, bound);
+    DGR_LAUNCH_CHECK();
+    return DGR_OK;
+}
+
 extern "C" dgr_status dgr_backproject(const float *proj, const dgr_grid *grid,
                                       const dgr_geometry *geom, float *volume, void *ws,
                                       size_t ws_bytes, void *stream) {
@@ -1405,7 +1422,8 @@ extern "C" dgr_status dgr_backproject(const float *proj, const dgr_grid *grid,
     absmax_bits<<<dim3((unsigned)std::min<int64_t>((nproj / 4 + 255) / 256 + 1, 2048)), dim3(256), 0, st>>>(
         proj, nproj, w.maxbits);
     DGR_LAUNCH_CHECK();
-    view_bound<<<dim3((unsigned)((geom->n_views + 255) / 256)), dim3(256), 0, st>>>(G, g, w.maxbits + 1);
+    view_bound<<<dim3((unsigned)((geom->n_views + 255) / 256)), dim3(256), 0, st>>>(G, g, w.maxbits + 1,
+                                                                                   nullptr);
     DGR_LAUNCH_CHECK();
     bp_scale<<<1, 1, 0, st>>>(w.maxbits, G.scale, headroom, w.scale);
     DGR_LAUNCH_CHECK();

@@ -66,6 +66,7 @@ _SIGS = {
     "dgr_project": ("st", ["p", "grid", "geom", "p", "p", "sz", "p"]),
     "dgr_project_l1": ("st", ["p", "grid", "geom", "p", "p", "p", "p", "sz", "p"]),
     "dgr_backproject": ("st", ["p", "grid", "geom", "p", "p", "sz", "p"]),
+    "dgr_backproject_weight_bound": ("st", ["grid", "geom", "p", "p"]),
     "dgr_project_siddon": ("st", ["p", "grid", "geom", "p", "p"]),
     "dgr_backproject_siddon_workspace": (ctypes.c_size_t, ["grid"]),
     "dgr_backproject_siddon": ("st", ["p", "grid", "geom", "p", "p", "sz", "p"]),
@@ -317,6 +318,15 @@ def dgr_backproject(proj, grid: GridSpec, geom: Geometry, views_dev, out=None,
     p, sz = ws.ptr_size(lib().dgr_project_workspace(ctypes.byref(g), ctypes.byref(G)))
     _check("dgr_backproject", lib().dgr_backproject(_ptr(proj), ctypes.byref(g), ctypes.byref(G),
                                                     _ptr(out), p, sz, _stream()))
+    return out
+
+
+def dgr_backproject_weight_bound(grid: GridSpec, geom: Geometry, views_dev):
+    """Per-view weight bound of the backprojection's fixed-point tile, float32 [n_views]."""
+    out = torch.empty(geom.n_views, dtype=torch.float32, device=views_dev.device)
+    g, G = c_grid(grid), c_geom(geom, views_dev)
+    _check("dgr_backproject_weight_bound",
+           lib().dgr_backproject_weight_bound(ctypes.byref(g), ctypes.byref(G), _ptr(out), _stream()))
     return out
 
 

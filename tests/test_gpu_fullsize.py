@@ -127,6 +127,26 @@ def test_full_backproject_constant_data(full):
     assert err < TOL and worst < 1e-5
 
 
+def test_full_weight_bound_holds(full):
+    """The device's per-view weight bound at full size (packed tile) is at
+    least the largest weight one tile point receives from a view (the
+    oracle's backprojection of ones on the grid widened by one voxel)."""
+    grid, geom, G, d, views, box = full
+    B = native.dgr_backproject_weight_bound(grid, geom, views).cpu().numpy().astype(np.float64)
+    say("full weight bound max", float(B.max()), "min", float(B.min()))
+    assert B.max() <= 512.0
+    h = 1.0 / np.asarray(grid.inv_h, np.float64)
+    dims = tuple(dd + 2 for dd in grid.dims)
+    lo = tuple(np.asarray(grid.lo, np.float64) - h)
+    for j in (0, 45):
+        g = np.ones((1, geom.nv, geom.nu))
+        W = oracle.backproject(g, dims, lo, grid.inv_h, geom.kind, geom.views[j:j + 1], geom.nu, geom.nv,
+                               geom.step, geom.length_scale)
+        peak = float(W.max()) / (float(geom.length_scale) * float(geom.step))
+        say("full weight bound view", j, "largest weight", round(peak, 3), "bound", float(B[j]))
+        assert peak <= B[j]
+
+
 def test_full_backproject_sampled_views_and_adjoint(full):
     grid, geom, G, d, views, box = full
     say("full backproject")

@@ -331,6 +331,45 @@ def test_backproject_zero_data(kind):
     assert not bool(torch.any(out != 0.0))
 
 
+def _weight_bound_cases():
+    """(name, grid, geometry, views to check against the oracle, packed?)"""
+    cases = [(k, grid, geom, [0, geom.n_views // 3], k != "cone") for k, (grid, geom) in _geoms().items()]
+    gf = inputs.GridSpec((48, 44, 40), (-1.0, -1.0 * 44 / 48, -1.0 * 40 / 48), (24.0, 24.0, 24.0))
+    fan = inputs.fan_geometry(8, 70, 40, 0.04, 1.0 / 24, 7.8125, 11.71875, 1.0 / 48)
+    v = fan.views.astype(np.float64).copy()
+    src = v[:, 0:3] / np.linalg.norm(v[:, 0:3], axis=1, keepdims=True)
+    v[:, 9:12] += 0.05 * np.linalg.norm(v[:, 9:12], axis=1, keepdims=True) * src
+    tilted = inputs.Geometry(2, v.astype(np.float32), fan.nu, fan.nv, fan.step, fan.length_scale)
+    cases += [("fan", gf, fan, [0, 3], True), ("fan_tilted", gf, tilted, [1, 5], True),
+              ("cone_dense", inputs.cube_grid(32), inputs.cone_workload(32, 8, 128, 0.8), [0, 3], False)]
+    return cases
+
+
+@pytest.mark.parametrize("case", [c[0] for c in _weight_bound_cases()])
+def test_backproject_weight_bound_holds(case):
+    """The per-view weight bound the backprojection computes on the device
+    (which sets the packed tile's scale) is at least the largest weight any
+    tile point receives from that view: the oracle's backprojection of ones
+    for that view alone, on the grid widened by one voxel per side (the
+    tiles' border points), divided by length_scale * step.  The largest bound
+    also picks the tile format expected for the geometry."""
+    name, grid, geom, sel, packed = next(c for c in _weight_bound_cases() if c[0] == case)
+    B = native.dgr_backproject_weight_bound(grid, geom, dev(geom.views)).cpu().numpy().astype(np.float64)
+    say("weight bound", name, "max", float(B.max()), "min", float(B.min()))
+    assert np.all(np.isfinite(B)) and np.all(B > 0)
+    assert (B.max() <= 512.0) == packed
+    h = 1.0 / np.asarray(grid.inv_h, np.float64)
+    dims = tuple(d + 2 for d in grid.dims)
+    lo = tuple(np.asarray(grid.lo, np.float64) - h)
+    for j in sel:
+        g = np.ones((1, geom.nv, geom.nu))
+        W = oracle.backproject(g, dims, lo, grid.inv_h, geom.kind, geom.views[j:j + 1], geom.nu, geom.nv,
+                               geom.step, geom.length_scale)
+        peak = float(W.max()) / (float(geom.length_scale) * float(geom.step))
+        say("weight bound", name, "view", j, "largest weight", round(peak, 3), "bound", float(B[j]))
+        assert peak <= B[j]
+
+
 def test_project_rays_with_disjoint_sample_ranges():
     """Two rays of one pixel bundle whose sample ranges are far apart
     ([-149, -50] and [50, 149]): the chunks between them hold no sample of
