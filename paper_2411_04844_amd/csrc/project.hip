@@ -297,15 +297,24 @@ __device__ __forceinline__ float wave_sum(float v) {
 // are affine in k, so the floors at the two ends of each ray's span bound
 // them), copies that box of the padded volume into LDS with coalesced rows,
 // and reads the eight taps of every sample from LDS.  The box is stored dense
-// (x fastest, its own extents as strides), so any shape up to kBoxCap cells
-// fits: rays of a cone-beam bundle are nearly parallel (about 16 x 16 x 13
-// cells for an 8-voxel chunk at 45 degrees), a fan-beam bundle's 16 rows
-// span 16 slices.  A chunk whose box exceeds kBoxCap reads its taps from the
-// padded copy instead.  Work-groups are numbered so each XCD (which receives
-// every 8th dispatched work-group) runs a contiguous range of bundles.
+// (x fastest, its own extents as strides), so any shape up to the box
+// capacity fits: rays of a cone-beam bundle are nearly parallel (about 16 x
+// 16 x 13 cells for an 8-voxel chunk at 45 degrees), a fan-beam bundle's 16
+// rows span 16 slices.  A chunk whose box exceeds the capacity reads its taps
+// from the padded copy instead.  Work-groups are numbered so each XCD (which
+// receives every 8th dispatched work-group) runs a contiguous range of
+// bundles.
+// NR rays per thread: a cone-beam work-group takes two 16 x 16 bundles side
+// by side in u (32 x 16 pixels), so the block-wide bound reductions, the
+// barriers and the row-wise staging of each box are shared by twice the
+// samples (70 VGPRs; a 22 KB box, so that seven work-groups fit a CU).  Fan
+// and parallel beams take one bundle with a larger box (28 KB, five
+// work-groups per CU): a fan bundle's 16 rows make taller boxes, and a chunk
+// that overflows reads its taps from HBM; 7,000 cells balance the two on the
+// fan-beam scans (a larger box costs a work-group per CU).
 // mode 0: write P_hat; mode 1: fused L1 (loss partial per work-group + dproj).
-constexpr int kBun = 16;         // bundle edge (pixels)
-constexpr int kBoxCap = 5600;    // LDS box (cells, 22 KB)
+constexpr int kBun = 16;  // bundle edge (pixels)
+constexpr int box_cap(int nr) { return nr == 1 ? 7000 : 5600; }  // LDS box (cells)
 constexpr int kFwdChunk = 16;    // samples per chunk
 
 __device__ __forceinline__ void block_bounds(int v[6], int (*red)[8], int wave, int lane) {
@@ -359,13 +368,14 @@ __device__ __forceinline__ void stage_box(float *box, const float *__restrict__ 
     }
 }
 
-template <int MODE>
+template <int MODE, int NR>
 __global__ __launch_bounds__(256) void project_bundles(const float *__restrict__ vp, PadDims p, DevGrid g,
                                                        GeomDev G, int tiles_u, int tiles_v, int64_t nb,
                                                        const float *__restrict__ target,
                                                        float *__restrict__ out, float inv_m,
                                                        float *__restrict__ partial) {
-    __shared__ float box[kBoxCap];
+    constexpr int kCap = box_cap(NR);
+    __shared__ float box[kCap];
     __shared__ int red[2][4][8];
     const int64_t per_xcd = (nb + kXcd - 1) / kXcd;
     const int64_t b = (int64_t)(blockIdx.x % kXcd) * per_xcd + blockIdx.x / kXcd;
@@ -375,44 +385,63 @@ __global__ __launch_bounds__(256) void project_bundles(const float *__restrict__
     const int j = (int)(b / per_view);
     const int rem = (int)(b - (int64_t)j * per_view);
     const int tv = rem / tiles_u, tu = rem - tv * tiles_u;
-    const int iu = tu * kBun + (t & (kBun - 1));
     const int iv = tv * kBun + (t / kBun);
-    const bool live = iu < G.nu && iv < G.nv;
-    Ray r;
-    int k0 = 0, k1 = -1;
-    bool ok = false;
-    if (live) {
-        ray_geom(G, g, j, iu, iv, r);
-        ok = support_range(r, g, &k0, &k1);
+    // ray q of this thread: pixel (iu[q], iv), bundle q of the tile
+    int iu[NR], k0[NR], k1[NR];
+    bool live[NR], ok[NR];
+    Ray r[NR];
+    int kr[6] = {0x7fffffff, 0, 0, -0x7fffffff, 0, 0};
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        iu[q] = tu * (kBun * NR) + q * kBun + (t & (kBun - 1));
+        live[q] = iu[q] < G.nu && iv < G.nv;
+        ok[q] = false;
+        k0[q] = 0;
+        k1[q] = -1;
+        if (live[q]) {
+            ray_geom(G, g, j, iu[q], iv, r[q]);
+            ok[q] = support_range(r[q], g, &k0[q], &k1[q]);
+        }
+        if (ok[q]) {
+            kr[0] = min(kr[0], k0[q]);
+            kr[3] = max(kr[3], k1[q]);
+        }
     }
-    int kr[6] = {ok ? k0 : 0x7fffffff, 0, 0, ok ? k1 : -0x7fffffff, 0, 0};
     block_bounds(kr, red[1], wave, lane);
     const int kmin = kr[0], kmax = kr[3];
     const int sy = (int)p.px, sz = (int)p.plane;
-    float acc = 0.0f;
+    float acc[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) acc[q] = 0.0f;
     int it = 0;
     for (int K = kmin; K <= kmax; K += kFwdChunk, ++it) {
         const int Ke = min(K + kFwdChunk - 1, kmax);
-        const int a = max(K, k0), e = min(Ke, k1);
-        const bool has = ok && a <= e;
+        int a[NR], e[NR];
+        bool has[NR];
         int bb[6] = {0x7fffffff, 0x7fffffff, 0x7fffffff, -0x7fffffff, -0x7fffffff, -0x7fffffff};
-        if (has) {
 #pragma unroll
-            for (int ax = 0; ax < 3; ++ax) {
-                const int fa = (int)((r.U[ax] + (long long)a * r.DU[ax]) >> 32);
-                const int fe = (int)((r.U[ax] + (long long)e * r.DU[ax]) >> 32);
-                bb[ax] = min(fa, fe);
-                bb[3 + ax] = max(fa, fe);
+        for (int q = 0; q < NR; ++q) {
+            a[q] = max(K, k0[q]);
+            e[q] = min(Ke, k1[q]);
+            has[q] = ok[q] && a[q] <= e[q];
+            if (has[q]) {
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax) {
+                    const int fa = (int)((r[q].U[ax] + (long long)a[q] * r[q].DU[ax]) >> 32);
+                    const int fe = (int)((r[q].U[ax] + (long long)e[q] * r[q].DU[ax]) >> 32);
+                    bb[ax] = min(bb[ax], min(fa, fe));
+                    bb[3 + ax] = max(bb[3 + ax], max(fa, fe));
+                }
             }
         }
         block_bounds(bb, red[it & 1], wave, lane);  // alternate buffers: no reuse race
-        // No ray of the bundle has a sample in this chunk (the union of the
-        // rays' sample ranges can have gaps): the bounds are still the
+        // No ray of the work-group has a sample in this chunk (the union of
+        // the rays' sample ranges can have gaps): the bounds are still the
         // sentinels.  The test is uniform over the work-group.
         if (bb[0] > bb[3]) continue;
         const int o[3] = {bb[0], bb[1], bb[2]};
         const int nx = bb[3] - bb[0] + 2, ny = bb[4] - bb[1] + 2, nz = bb[5] - bb[2] + 2;
-        if ((int64_t)nx * ny * nz <= kBoxCap) {
+        if ((int64_t)nx * ny * nz <= kCap) {
             // taps of the chunk: padded voxels o .. o + n - 1, inside the padded
             // copy
             const float *src = vp + ((int64_t)o[2] * p.py + o[1]) * p.px + o[0];
@@ -421,25 +450,31 @@ __global__ __launch_bounds__(256) void project_bundles(const float *__restrict__
             else
                 stage_box<false>(box, src, nx, ny, nz, (unsigned)p.px, (unsigned)p.plane);
             __syncthreads();
-            if (has) march_box(box, nx, nx * ny, o, r, a, e, acc);
+#pragma unroll
+            for (int q = 0; q < NR; ++q)
+                if (has[q]) march_box(box, nx, nx * ny, o, r[q], a[q], e[q], acc[q]);
             __syncthreads();
-        } else if (has) {
+        } else {
             const int o0[3] = {0, 0, 0};
-            march_span(vp, sy, sz, o0, r, a, e, acc);
+#pragma unroll
+            for (int q = 0; q < NR; ++q)
+                if (has[q]) march_span(vp, sy, sz, o0, r[q], a[q], e[q], acc[q]);
         }
     }
-    const float val = acc * G.scale;
-    const int64_t ri = ((int64_t)j * G.nv + iv) * G.nu + iu;
-    if (MODE == 0) {
-        if (live) out[ri] = val;
-        return;
-    }
     float absr = 0.0f;
-    if (live) {
-        const float res = val - target[ri];
-        out[ri] = res > 0.0f ? inv_m : (res < 0.0f ? -inv_m : 0.0f);
-        absr = fabsf(res);
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        const float val = acc[q] * G.scale;
+        const int64_t ri = ((int64_t)j * G.nv + iv) * G.nu + iu[q];
+        if (MODE == 0) {
+            if (live[q]) out[ri] = val;
+        } else if (live[q]) {
+            const float res = val - target[ri];
+            out[ri] = res > 0.0f ? inv_m : (res < 0.0f ? -inv_m : 0.0f);
+            absr += fabsf(res);
+        }
     }
+    if (MODE == 0) return;
     __shared__ float ws[4];
     absr = wave_sum(absr);
     if (lane == 0) ws[wave] = absr;
@@ -1251,8 +1286,14 @@ struct ProjWs {
     size_t bytes;
 };
 
-int64_t ray_blocks(const dgr_geometry *G, int *tu, int *tv) {
-    *tu = (G->nu + kBun - 1) / kBun;
+// rays per thread of the forward work-groups (see project_bundles): two for
+// cone beams, one for fan and parallel beams
+inline int fwd_rays_per_thread(const dgr_geometry *G) { return G->kind == DGR_CONE ? 2 : 1; }
+
+// Forward work-groups of a scan with nr rays per thread: tiles of (16 nr) x 16
+// pixels.
+int64_t ray_blocks(const dgr_geometry *G, int *tu, int *tv, int nr) {
+    *tu = (G->nu + kBun * nr - 1) / (kBun * nr);
     *tv = (G->nv + kBun - 1) / kBun;
     return (int64_t)G->n_views * (*tu) * (*tv);
 }
@@ -1264,7 +1305,7 @@ ProjWs carve_proj_ws(void *ws, const dgr_grid *grid, const dgr_geometry *geom) {
     int tu, tv;
     Carver f(ws);
     w.vpad = f.take<float>(pad_count(grid));
-    w.partial = f.take<float>(ray_blocks(geom, &tu, &tv));
+    w.partial = f.take<float>(ray_blocks(geom, &tu, &tv, fwd_rays_per_thread(geom)));
     Carver b(ws);
     const Bricks bk = bricks_of(grid);
     w.staging = b.take<long long>(bk.count() * kBT3);
@@ -1346,11 +1387,16 @@ static dgr_status project_impl(const float *volume, const dgr_grid *grid, const 
     pad_volume<<<dim3(grid_stride_blocks(pad_count(grid))), dim3(256), 0, st>>>(volume, g, p, w.vpad);
     DGR_LAUNCH_CHECK();
     int tu, tv;
-    const int64_t nb = ray_blocks(geom, &tu, &tv);
+    const int nr = fwd_rays_per_thread(geom);
+    const int64_t nb = ray_blocks(geom, &tu, &tv, nr);
     const double m = (double)geom->n_views * geom->nu * geom->nv;
     const int64_t launched = (nb + kXcd - 1) / kXcd * kXcd;
-    project_bundles<MODE><<<dim3((unsigned)launched), dim3(256), 0, st>>>(
-        w.vpad, p, g, geom_dev(geom), tu, tv, nb, target, out, (float)(1.0 / m), w.partial);
+    if (nr == 2)
+        project_bundles<MODE, 2><<<dim3((unsigned)launched), dim3(256), 0, st>>>(
+            w.vpad, p, g, geom_dev(geom), tu, tv, nb, target, out, (float)(1.0 / m), w.partial);
+    else
+        project_bundles<MODE, 1><<<dim3((unsigned)launched), dim3(256), 0, st>>>(
+            w.vpad, p, g, geom_dev(geom), tu, tv, nb, target, out, (float)(1.0 / m), w.partial);
     DGR_LAUNCH_CHECK();
     if (MODE == 1) {
         finish_loss<<<1, 1024, 0, st>>>(w.partial, nb, 1.0 / m, loss);

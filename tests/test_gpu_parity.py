@@ -241,6 +241,40 @@ def test_project_l1_parity(kind):
     assert mism.mean() < 2e-3
 
 
+def _coarse_geoms():
+    """Detectors whose pixels are about four voxels wide at the isocentre, so
+    that a forward work-group's rays (16 x 16 pixels, 32 x 16 for cone beams)
+    cover about 64 x 64 voxels: every chunk's box of cells (at least 10 x 66 x
+    66) exceeds the LDS box and the taps come from the padded copy in HBM.
+    Both detectors leave ragged tiles (24 = 16 + 8 columns, 40 = 32 + 8)."""
+    grid_p = inputs.cube_grid(64)
+    h = 2.0 / 64
+    par = inputs.parallel_geometry(12, 24, 24, 4 * h, h / 2)
+    grid_c = inputs.GridSpec((48, 44, 40), (-1.0, -1.0 * 44 / 48, -1.0 * 40 / 48), (24.0, 24.0, 24.0))
+    cone = inputs.cone_geometry(8, 40, 20, 0.25, 7.8125, 11.71875, 1.0 / 48, arc=2 * math.pi)
+    return {"parallel": (grid_p, par), "cone": (grid_c, cone)}
+
+
+@pytest.mark.parametrize("kind", ["parallel", "cone"])
+def test_project_parity_box_overflow(kind):
+    grid, geom = _coarse_geoms()[kind]
+    say("project box overflow", kind)
+    V = _rand_volume(grid, 92)
+    want = oracle.project(V.astype(np.float64), grid.dims, grid.lo, grid.inv_h, geom.kind, geom.views,
+                          geom.nu, geom.nv, geom.step, geom.length_scale)
+    assert np.count_nonzero(want) > 0.2 * want.size
+    views = dev(geom.views)
+    got = native.dgr_project(dev(V), grid, geom, views).cpu().numpy()
+    say("project box overflow", kind, "rel_l2", rel_l2(got, want))
+    assert rel_l2(got, want) < TOL
+    y = np.random.default_rng(8).uniform(0, want.max(), size=want.shape).astype(np.float32)
+    loss, g = native.dgr_project_l1(dev(V), dev(y), grid, geom, views)
+    wl, wg = oracle.l1(want, y)
+    assert abs(float(loss) - wl) / wl < TOL
+    mism = np.sign(g.cpu().numpy()) != np.sign(wg)
+    assert np.all(np.abs(want - y.astype(np.float64))[mism] < 1e-5 * np.abs(want).max())
+
+
 @pytest.mark.parametrize("kind", BACKPROJECT_KINDS)
 def test_backproject_parity_and_adjoint(kind):
     grid, geom = _geoms()[kind]
