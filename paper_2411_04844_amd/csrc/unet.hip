@@ -29,12 +29,19 @@
 //   conv3_tile   implicit GEMM (M = voxels, N = output channels,
 //                K = 27 x input channels) on v_mfma_f32_16x16x32_bf16 over
 //                16 x 4 x 4 voxel tiles whose halo is staged in LDS once per
-//                32-channel block and read by all 27 taps.  The data gradient
-//                is the same kernel with transposed, tap-reversed weights.
+//                32-channel block and read by all 27 taps (two LDS reads per
+//                three taps along x, the middle one formed by DPP row
+//                shifts); weights in a fragment-major layout, so that a wave
+//                reads each B fragment as 1 KB in one piece, prefetched one
+//                (dz, dy) row ahead.  The data gradient is the same kernel
+//                with transposed, tap-reversed weights.
 //   conv3_wgrad  dW[t] = dY^T shift_t(X): K = voxels; per 16 x 4 x 4 voxel
-//                tile dY and the x-shifted X halo are transposed into LDS and
-//                9 taps share each dY fragment; split over chunks of tiles
-//                into binary32 partials summed in a fixed order.
+//                tile dY and the x-shifted X halo are transposed into LDS
+//                (bank-swizzled columns) and 9 taps share each dY fragment;
+//                the next tile's loads are in flight during the current
+//                tile's MFMAs; split over chunks of tiles into binary32
+//                partials summed in a fixed order, all work-groups of a chunk
+//                on one XCD.
 //   conv1_*      the 1-channel first layer on the VALU (K = 27).
 //   pooling, upsampling (with the ReLU masks of the backward fused in), the
 //   1x1 head and the loss are elementwise VALU kernels.
@@ -92,7 +99,36 @@ constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2;
 constexpr int kHalo = kHX * kHY * kHZ;  // 648 voxels
 constexpr int kHPitch = 40;             // u16 per halo voxel (32 used)
 
-template <int NT>
+// Index of weight (tap t, output channel o, input channel c) of a cout x cin
+// layer in the fragment-major layout: per tap, 32-channel input block and
+// 16-channel output block, the 1 KB B fragment of v_mfma_f32_16x16x32_bf16 in
+// lane order (lane 16 g + r holds output channel 16 ob + r and input channels
+// 32 kb + 8 g .. + 7), so that a wave reads a fragment as 1 KB in one piece.
+// The plain layout [27][cout][cin] puts a fragment's 16 rows cin apart.
+__host__ __device__ __forceinline__ int64_t frag_index(int t, int o, int c, int cout, int cin) {
+    const int64_t f = ((int64_t)t * (cin >> 5) + (c >> 5)) * (cout >> 4) + (o >> 4);
+    return f * 512 + (((c & 31) >> 3) * 16 + (o & 15)) * 8 + (c & 7);
+}
+
+// The A fragment one voxel to the right: lane r of each row of 16 takes
+// lane r + 1 of lo (DPP row shift left), lane 15 takes lane 14 of hi (row
+// shift right), lo and hi being the fragments at offsets 0 and 2 in x.
+__device__ __forceinline__ bf16x8 mid_fragment(const bf16x8 &lo, const bf16x8 &hi) {
+    const u32x4 a = __builtin_bit_cast(u32x4, lo), b = __builtin_bit_cast(u32x4, hi);
+    u32x4 o;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int edge = __builtin_amdgcn_update_dpp(0, (int)b[k], 0x111, 0xF, 0xF, false);  // row_shr:1
+        o[k] = (unsigned)__builtin_amdgcn_update_dpp(edge, (int)a[k], 0x101, 0xF, 0xF, false);  // row_shl:1
+    }
+    return __builtin_bit_cast(bf16x8, o);
+}
+
+// The 27 taps run as 9 (dz, dy) rows of 3: per row a wave reads its A
+// fragments at dx = -1 and dx = +1 from the halo and forms dx = 0 from them
+// with two DPP moves per register, two LDS reads for three taps.  FRAG: the
+// weights are in the fragment-major layout.
+template <int NT, bool FRAG>
 __global__ __launch_bounds__(256) void conv3_tile(const u16 *__restrict__ x, int xs, Vol d, int cin,
                                                   const u16 *__restrict__ w,
                                                   const float *__restrict__ bias, int cout, int relu,
@@ -107,40 +143,88 @@ __global__ __launch_bounds__(256) void conv3_tile(const u16 *__restrict__ x, int
     const int ty = tile % nty, tz = tile / nty;
     const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * kTZ;
     const int co0 = blockIdx.y * (16 * NT);
+    // per tap and per output block of 16: strides between B fragments (u16)
+    const int64_t tstride = FRAG ? (int64_t)(cin >> 5) * (cout >> 4) * 512 : (int64_t)cout * cin;
+    const int64_t nstride = FRAG ? 512 : (int64_t)16 * cin;
     f32x4 acc[4][NT];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
         for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    // 16-byte halo loads per thread (the last partial), issued kBatch at a time
+    // before their LDS stores (all of them where the registers allow: with
+    // 64 output channels the accumulators leave room for half)
+    constexpr int kLoads = (kHalo * 4 + 255) / 256;
+    constexpr int kBatch = NT >= 4 ? (kLoads + 1) / 2 : kLoads;
     for (int kb = 0; kb < cin; kb += 32) {
-        for (int q = threadIdx.x; q < kHalo * 4; q += 256) {
-            const int hv = q >> 2, c8 = (q & 3) * 8;
-            const int hx = hv % kHX, hr = hv / kHX;
-            const int hy = hr % kHY, hz = hr / kHY;
-            const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
-            u32x4 val = u32x4{0u, 0u, 0u, 0u};
-            if (gx >= 0 && gy >= 0 && gz >= 0 && gx < d.nx && gy < d.ny && gz < d.nz)
-                val = *reinterpret_cast<const u32x4 *>(x + (((int64_t)gz * d.ny + gy) * d.nx + gx) * xs + kb + c8);
-            *reinterpret_cast<u32x4 *>(halo + hv * kHPitch + c8) = val;
+#pragma unroll
+        for (int u0 = 0; u0 < kLoads; u0 += kBatch) {
+            u32x4 val[kBatch];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const int q = threadIdx.x + 256 * (u0 + u);
+                const int hv = q >> 2, c8 = (q & 3) * 8;
+                const int hx = hv % kHX, hr = hv / kHX;
+                const int hy = hr % kHY, hz = hr / kHY;
+                const int gx = x0 + hx - 1, gy = y0 + hy - 1, gz = z0 + hz - 1;
+                val[u] = u32x4{0u, 0u, 0u, 0u};
+                if (u0 + u < kLoads && q < kHalo * 4 && gx >= 0 && gy >= 0 && gz >= 0 && gx < d.nx && gy < d.ny &&
+                    gz < d.nz)
+                    val[u] =
+                        *reinterpret_cast<const u32x4 *>(x + (((int64_t)gz * d.ny + gy) * d.nx + gx) * xs + kb + c8);
+            }
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const int q = threadIdx.x + 256 * (u0 + u);
+                if (u0 + u < kLoads && q < kHalo * 4)
+                    *reinterpret_cast<u32x4 *>(halo + (q >> 2) * kHPitch + (q & 3) * 8) = val[u];
+            }
         }
         __syncthreads();
-#pragma unroll 3
-        for (int t = 0; t < 27; ++t) {
-            const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-            bf16x8 a[4], b[NT];
+        const u16 *wk = FRAG ? w + ((int64_t)(kb >> 5) * (cout >> 4) + (co0 >> 4)) * 512 + lane * 8
+                             : w + (int64_t)(co0 + r) * cin + kb + 8 * g;
+        // B fragments of the three taps of row p; those of row p + 1 are
+        // loaded before row p's MFMAs
+        bf16x8 b[3][NT];
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+            for (int n = 0; n < NT; ++n)
+                b[dx][n] = *reinterpret_cast<const bf16x8 *>(wk + (int64_t)dx * tstride + n * nstride);
+#pragma unroll 1
+        for (int p = 0; p < 9; ++p) {
+            const int dz = p / 3 - 1, dy = p % 3 - 1;
+            bf16x8 bn[3][NT];
+            if (p < 8) {
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+                    for (int n = 0; n < NT; ++n)
+                        bn[dx][n] = *reinterpret_cast<const bf16x8 *>(wk + (int64_t)(3 * p + 3 + dx) * tstride +
+                                                                     n * nstride);
+            }
+            bf16x8 a[3][4];
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
-                const int hv = ((wave + 1 + dz) * kHY + (m + 1 + dy)) * kHX + (r + 1 + dx);
-                a[m] = *reinterpret_cast<const bf16x8 *>(halo + hv * kHPitch + 8 * g);
+                // halo x index r (dx = -1) and r + 2 (dx = +1)
+                const int hv = ((wave + 1 + dz) * kHY + (m + 1 + dy)) * kHX + r;
+                a[0][m] = *reinterpret_cast<const bf16x8 *>(halo + hv * kHPitch + 8 * g);
+                a[2][m] = *reinterpret_cast<const bf16x8 *>(halo + (hv + 2) * kHPitch + 8 * g);
+                a[1][m] = mid_fragment(a[0][m], a[2][m]);
             }
-            const u16 *wp = w + ((int64_t)t * cout + co0 + r) * cin + kb + 8 * g;
 #pragma unroll
-            for (int n = 0; n < NT; ++n) b[n] = *reinterpret_cast<const bf16x8 *>(wp + (int64_t)n * 16 * cin);
+            for (int dx = 0; dx < 3; ++dx)
 #pragma unroll
-            for (int m = 0; m < 4; ++m)
+                for (int m = 0; m < 4; ++m)
 #pragma unroll
-                for (int n = 0; n < NT; ++n)
-                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b[n], acc[m][n], 0, 0, 0);
+                    for (int n = 0; n < NT; ++n)
+                        acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[dx][m], b[dx][n], acc[m][n], 0, 0, 0);
+            if (p < 8) {
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx)
+#pragma unroll
+                    for (int n = 0; n < NT; ++n) b[dx][n] = bn[dx][n];
+            }
         }
         __syncthreads();
     }
@@ -168,9 +252,9 @@ __global__ __launch_bounds__(256) void conv3_tile(const u16 *__restrict__ x, int
 }
 
 // ---- weight gradient ------------------------------------------------------------
-// dW[t][co][ci] = sum_v dY[v][co] X[v + t][ci]: K = voxels.  Grid: x = 3 x
-// shifts (dx) x (cout / 32) x (cin / 32) channel blocks, y = chunks of the
-// 16 x 4 x 4 voxel tiles (the tiles of conv3_tile).  Per tile a work-group
+// dW[t][co][ci] = sum_v dY[v][co] X[v + t][ci]: K = voxels.  Work-groups:
+// 3 shifts (dx) x (cout / 32) x (cin / 32) channel blocks for each chunk of
+// the 16 x 4 x 4 voxel tiles (the tiles of conv3_tile).  Per tile a work-group
 // stages, transposed in LDS, dY of the tile's 256 voxels ([co][v], v = x +
 // 16 (y + 4 z)) and X over the tile's (dy, dz) halo shifted by its dx
 // ([ci][hz][hy][x], 6 x 6 rows of 16), so that the 8-voxel K slice of a lane
@@ -182,6 +266,13 @@ __global__ __launch_bounds__(256) void conv3_tile(const u16 *__restrict__ x, int
 constexpr int kWgPitchA = 256 + 8;      // u16 per dY row (one channel, 256 voxels)
 constexpr int kWgPitchB = 6 * 6 * 16 + 8;  // u16 per X row (one channel, 6 x 6 x 16 voxels)
 
+// Column swizzle of the transposed tiles: row c (a channel) stores its 16-byte
+// chunks (8 voxels) XOR-ed with 2 ((c / 8) mod 4), so that the four loader
+// lanes of a voxel group, whose channel octets put their rows 8 apart (the
+// same LDS banks for any 16-byte-aligned pitch), write different banks.  The
+// XOR stays inside aligned groups of 8 chunks.
+__device__ __forceinline__ int wg_swz(int row, int col) { return col ^ (((row >> 3) & 3) << 4); }
+
 __device__ __forceinline__ void store_transposed(u16 *dst, int pitch, int c8, int vg, const u32x4 (&q)[4]) {
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -191,7 +282,7 @@ __device__ __forceinline__ void store_transposed(u16 *dst, int pitch, int c8, in
             ((unsigned long long)((q[1][j >> 1] >> sh) & 0xffffu) << 16) |
             ((unsigned long long)((q[2][j >> 1] >> sh) & 0xffffu) << 32) |
             ((unsigned long long)((q[3][j >> 1] >> sh) & 0xffffu) << 48);
-        *reinterpret_cast<unsigned long long *>(dst + (c8 + j) * pitch + vg) = w;
+        *reinterpret_cast<unsigned long long *>(dst + (c8 + j) * pitch + wg_swz(c8 + j, vg)) = w;
     }
 }
 
@@ -200,63 +291,88 @@ __device__ __forceinline__ u32x4 load8(const u16 *p, const Vol &d, int gx, int g
     return *reinterpret_cast<const u32x4 *>(p + (((int64_t)gz * d.ny + gy) * d.nx + gx) * s);
 }
 
-__global__ __launch_bounds__(256) void conv3_wgrad(const u16 *__restrict__ x, int xs, Vol d, int cin,
-                                                   const u16 *__restrict__ dy, int dys, int cout,
+// One-dimensional grid of ncombo x (nc rounded up to a multiple of 8)
+// work-groups, ncombo = 3 shifts x (cout / 32) x (cin / 32).  The dispatcher
+// deals work-groups round-robin to the 8 XCDs, so XCD L mod 8 runs work-groups
+// L, L + 8, ...; they are given, in order, every combination of chunk
+// 8 k + L mod 8 for k = 0, 1, ...: the combinations of a chunk read the same
+// tiles of X and dY, which then stay in that XCD's L2.
+constexpr int kXcds = 8;
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void conv3_wgrad(const u16 *__restrict__ x, int xs, Vol d, int cin,
+                                                   const u16 *__restrict__ dy, int dys, int cout, int nc,
                                                    float *__restrict__ part) {
     __shared__ __attribute__((aligned(16))) u16 At[32 * kWgPitchA];  // [co][v]
     __shared__ __attribute__((aligned(16))) u16 Bt[32 * kWgPitchB];  // [ci][hz][hy][x]
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, g = lane >> 4;
     const int n_ci = cin / 32, n_co = cout / 32;
-    int blk = blockIdx.x;
+    const int ncombo = 3 * n_co * n_ci;
+    const int slot = (int)(blockIdx.x / kXcds);
+    const int chunk = (slot / ncombo) * kXcds + (int)(blockIdx.x % kXcds);
+    if (chunk >= nc) return;  // whole work-group
+    int blk = slot % ncombo;
     const int ib = blk % n_ci;
     blk /= n_ci;
     const int cb = blk % n_co;
     const int dx = blk / n_co - 1;
     const int ntx = (d.nx + kTX - 1) / kTX, nty = (d.ny + kTY - 1) / kTY, ntz = (d.nz + kTZ - 1) / kTZ;
     const int64_t ntiles = (int64_t)ntx * nty * ntz;
-    const int64_t t_begin = ntiles * blockIdx.y / gridDim.y, t_end = ntiles * (blockIdx.y + 1) / gridDim.y;
+    const int64_t t_begin = ntiles * chunk / nc, t_end = ntiles * (chunk + 1) / nc;
     const int msub = (wave >> 1) * 16, nsub = (wave & 1) * 16;
     f32x4 acc[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) acc[k] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    const int c8 = (tid & 3) * 8;  // 8 channels of every loader task
-    for (int64_t tile = t_begin; tile < t_end; ++tile) {
+    // Loader tasks of a tile: dY, 64 groups of 4 voxels (same row) x 4 channel
+    // octets, one per thread; X, the halo rows (hz, hy) shifted by dx, 144
+    // groups x 4 octets, two or three per thread.  The next tile's loads are
+    // issued before the current tile's MFMAs and held in registers.
+    const int c8 = (tid & 3) * 8;  // 8 channels of every loader task (task = tid mod 4)
+    const int vga = (tid >> 2) * 4;  // dY: tile voxels vga .. vga + 3
+    u32x4 qa[4], qb[3][4];
+    auto load_tile = [&](int64_t tile) {
         const int tx = (int)(tile % ntx), ty = (int)((tile / ntx) % nty), tz = (int)(tile / ((int64_t)ntx * nty));
         const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * kTZ;
-        {   // dY: 64 groups of 4 voxels x 4 channel octets, one task per thread
-            const int vg = (tid >> 2) * 4;  // tile voxels vg .. vg + 3 (same row)
-            const int lx = vg & 15, ly = (vg >> 4) & 3, lz = vg >> 6;
-            u32x4 q[4];
+        const int lx = vga & 15, ly = (vga >> 4) & 3, lz = vga >> 6;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) q[i] = load8(dy + cb * 32 + c8, d, x0 + lx + i, y0 + ly, z0 + lz, dys);
-            store_transposed(At, kWgPitchA, c8, vg, q);
+        for (int i = 0; i < 4; ++i) qa[i] = load8(dy + cb * 32 + c8, d, x0 + lx + i, y0 + ly, z0 + lz, dys);
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            const int task = tid + 256 * u;
+            if (task < 144 * 4) {
+                const int vg = (task >> 2) * 4;  // halo voxels vg .. vg + 3 (same row of 16)
+                const int hx = vg & 15, hr = vg >> 4, hy = hr % 6, hz = hr / 6;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    qb[u][i] = load8(x + ib * 32 + c8, d, x0 + hx + i + dx, y0 + hy - 1, z0 + hz - 1, xs);
+            }
         }
-        // X rows (hz, hy) of the halo, shifted by dx: 144 groups x 4 octets
-        for (int task = tid; task < 144 * 4; task += 256) {
-            const int vg = (task >> 2) * 4;  // halo voxels vg .. vg + 3 (same row of 16)
-            const int hx = vg & 15, hr = vg >> 4, hy = hr % 6, hz = hr / 6;
-            const int oc8 = (task & 3) * 8;
-            u32x4 q[4];
+    };
+    if (t_begin < t_end) load_tile(t_begin);
+    for (int64_t tile = t_begin; tile < t_end; ++tile) {
+        store_transposed(At, kWgPitchA, c8, vga, qa);
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                q[i] = load8(x + ib * 32 + oc8, d, x0 + hx + i + dx, y0 + hy - 1, z0 + hz - 1, xs);
-            store_transposed(Bt, kWgPitchB, oc8, vg, q);
+        for (int u = 0; u < 3; ++u) {
+            const int task = tid + 256 * u;
+            if (task < 144 * 4) store_transposed(Bt, kWgPitchB, c8, (task >> 2) * 4, qb[u]);
         }
         __syncthreads();
+        if (tile + 1 < t_end) load_tile(tile + 1);
 #pragma unroll
         for (int kk = 0; kk < 8; ++kk) {
             // K block kk: tile voxels 32 kk .. 32 kk + 31, i.e. rows (y, z) =
             // (2 kk, 2 kk + 1) in units of 16; lane g takes row 2 kk + g / 2,
             // x = 8 (g % 2) .. + 7
-            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(At + (msub + r) * kWgPitchA + kk * 32 + 8 * g);
+            const bf16x8 a =
+                *reinterpret_cast<const bf16x8 *>(At + (msub + r) * kWgPitchA + wg_swz(msub + r, kk * 32 + 8 * g));
             const int row = 2 * kk + (g >> 1);  // = y + 4 z of the tile
             const int ly = row & 3, lz = row >> 2, xo = 8 * (g & 1);
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
                 const int dz = k / 3 - 1, dyy = k % 3 - 1;
                 const int hrow = (lz + 1 + dz) * 6 + (ly + 1 + dyy);
-                const bf16x8 b = *reinterpret_cast<const bf16x8 *>(Bt + (nsub + r) * kWgPitchB + hrow * 16 + xo);
+                const bf16x8 b =
+                    *reinterpret_cast<const bf16x8 *>(Bt + (nsub + r) * kWgPitchB + wg_swz(nsub + r, hrow * 16 + xo));
                 acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[k], 0, 0, 0);
             }
         }
@@ -266,7 +382,7 @@ __global__ __launch_bounds__(256) void conv3_wgrad(const u16 *__restrict__ x, in
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
         const int t = (k / 3) * 9 + (k % 3) * 3 + (dx + 1);  // (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)
-        float *out = part + ((int64_t)blockIdx.y * 27 + t) * cout * cin;
+        float *out = part + ((int64_t)chunk * 27 + t) * cout * cin;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int co = cb * 32 + msub + 4 * g + i, ci = ib * 32 + nsub + r;
@@ -403,8 +519,10 @@ __global__ __launch_bounds__(256) void cast_weights(const float *__restrict__ W,
     const int rem = (int)(i - (int64_t)t * cout * cin);
     const int o = rem / cin, ci = rem - o * cin;
     const u16 h = f2bf(W[i]);
-    wb[i] = h;
-    wt[((int64_t)(26 - t) * cin + ci) * cout + o] = h;
+    // fragment-major (frag_index): wb for the forward (cout x cin), wt, with
+    // the taps reversed and the channel roles swapped, for the data gradient
+    wb[frag_index(t, o, ci, cout, cin)] = h;
+    wt[frag_index(26 - t, ci, o, cin, cout)] = h;
 }
 
 // ---- pooling, upsampling, skip gradients ---------------------------------------------------
@@ -762,14 +880,22 @@ dgr_status check_unet(const int32_t dims[3], int B, Net *n, void *ws, size_t ws_
     return DGR_OK;
 }
 
+// frag: w is in the fragment-major layout (the library's casts), else plain
+// [27][cout][cin].
 dgr_status launch_conv(const u16 *x, int xs, const Vol &d, int cin, const u16 *w, const float *bias,
-                       int cout, int relu, u16 *y, int ys, hipStream_t st) {
+                       int cout, int relu, u16 *y, int ys, hipStream_t st, bool frag = true) {
     const int64_t tiles = (int64_t)((d.nx + kTX - 1) / kTX) * ((d.ny + kTY - 1) / kTY) * ((d.nz + kTZ - 1) / kTZ);
-    const dim3 grid((unsigned)tiles, (unsigned)(cout % 64 == 0 ? cout / 64 : cout / 32));
-    if (cout % 64 == 0)
-        conv3_tile<4><<<grid, dim3(256), 0, st>>>(x, xs, d, cin, w, bias, cout, relu, y, ys);
+    // output channels per work-group: 64 where they divide, else 32
+    const int per = cout % 64 == 0 ? 64 : 32;
+    const dim3 grid((unsigned)tiles, (unsigned)(cout / per));
+    if (per == 64 && frag)
+        conv3_tile<4, true><<<grid, dim3(256), 0, st>>>(x, xs, d, cin, w, bias, cout, relu, y, ys);
+    else if (frag)
+        conv3_tile<2, true><<<grid, dim3(256), 0, st>>>(x, xs, d, cin, w, bias, cout, relu, y, ys);
+    else if (per == 64)
+        conv3_tile<4, false><<<grid, dim3(256), 0, st>>>(x, xs, d, cin, w, bias, cout, relu, y, ys);
     else
-        conv3_tile<2><<<grid, dim3(256), 0, st>>>(x, xs, d, cin, w, bias, cout, relu, y, ys);
+        conv3_tile<2, false><<<grid, dim3(256), 0, st>>>(x, xs, d, cin, w, bias, cout, relu, y, ys);
     DGR_LAUNCH_CHECK();
     return DGR_OK;
 }
@@ -778,8 +904,8 @@ dgr_status launch_conv(const u16 *x, int xs, const Vol &d, int cin, const u16 *w
 dgr_status launch_wgrad(const u16 *x, int xs, const Vol &d, int cin, const u16 *dy, int cout, float *part,
                         float *dW, float *db, hipStream_t st) {
     const int nc = wgrad_chunks(d.V);
-    const dim3 grid((unsigned)(3 * (cout / 32) * (cin / 32)), (unsigned)nc);
-    conv3_wgrad<<<grid, dim3(256), 0, st>>>(x, xs, d, cin, dy, cout, cout, part);
+    const int64_t blocks = (int64_t)3 * (cout / 32) * (cin / 32) * ((nc + kXcds - 1) / kXcds * kXcds);
+    conv3_wgrad<<<dim3((unsigned)blocks), dim3(256), 0, st>>>(x, xs, d, cin, dy, cout, cout, nc, part);
     DGR_LAUNCH_CHECK();
     const int64_t n = 27LL * cout * cin;
     sum_chunks<<<blocks_for(n), 256, 0, st>>>(part, nc, n, dW);
@@ -958,7 +1084,7 @@ extern "C" dgr_status dgr_conv3_forward(const uint16_t *x, int32_t x_stride, con
     Vol d{dims[0], dims[1], dims[2], (int64_t)dims[0] * dims[1] * dims[2]};
     DGR_CHECK(dims[0] >= 1 && dims[1] >= 1 && dims[2] >= 1, "dims must be >= 1");
     return launch_conv(reinterpret_cast<const u16 *>(x), x_stride, d, cin, reinterpret_cast<const u16 *>(w),
-                       bias, cout, relu, reinterpret_cast<u16 *>(y), y_stride, as_stream(stream));
+                       bias, cout, relu, reinterpret_cast<u16 *>(y), y_stride, as_stream(stream), false);
 }
 
 extern "C" size_t dgr_conv3_grad_workspace(const int32_t dims[3], int32_t cin, int32_t cout) {
