@@ -402,22 +402,32 @@ __global__ __launch_bounds__(256) void sum_chunks(const float *__restrict__ part
 }
 
 // Per-channel sums of a bf16 [V][s] slice (channels 0..C-1), C <= 256 and a
-// divisor of 256: part[block][c] over the block's voxel range, with 256 / C
-// voxel lanes per channel summed in a fixed order at the end.
+// multiple of 8: part[block][c] over the block's voxel range.  Each thread
+// reads 8 channels per voxel; lanes = 256 / (C / 8) threads share a channel
+// octet, taking every lanes-th voxel, and their sums are added in a fixed
+// order at the end (threads beyond lanes x C / 8 compute sums nobody reads).
 constexpr int kSumBlocks = 1024;
 __global__ __launch_bounds__(256) void channel_sums(const u16 *__restrict__ a, int s, int C, int64_t V,
                                                     float *__restrict__ part) {
-    __shared__ float red[256];
-    const int c = threadIdx.x % C, j = threadIdx.x / C, lanes = 256 / C;
+    __shared__ float red[256 * 8];
+    // thread: 8 channels c8 .. c8 + 7 (one 16-byte load per voxel) of every
+    // lanes-th voxel of the block's range (C % 8 == 0, s % 8 == 0)
+    const int groups = C / 8;
+    const int c8 = (threadIdx.x % groups) * 8, j = threadIdx.x / groups, lanes = 256 / groups;
     const int64_t per = (V + gridDim.x - 1) / gridDim.x;
     const int64_t v0 = (int64_t)blockIdx.x * per, v1 = min(V, v0 + per);
-    float acc = 0.0f;
-    for (int64_t v = v0 + j; v < v1; v += lanes) acc += bf2f(a[v * s + c]);
-    red[threadIdx.x] = acc;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int64_t v = v0 + j; v < v1; v += lanes) {
+        const u32x4 q = *reinterpret_cast<const u32x4 *>(a + v * s + c8);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k] += bf2f((u16)(q[k >> 1] >> (16 * (k & 1))));
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) red[threadIdx.x * 8 + k] = acc[k];
     __syncthreads();
-    if (j == 0) {
+    for (int c = threadIdx.x; c < C; c += 256) {
         float t = 0.0f;
-        for (int q = 0; q < lanes; ++q) t += red[q * C + c];
+        for (int q = 0; q < lanes; ++q) t += red[(q * groups + c / 8) * 8 + c % 8];
         part[(int64_t)blockIdx.x * C + c] = t;
     }
 }
@@ -444,11 +454,21 @@ __global__ __launch_bounds__(256) void conv1_fwd(const float *__restrict__ x, Vo
         const bool in = xx >= 0 && yy >= 0 && zz >= 0 && xx < d.nx && yy < d.ny && zz < d.nz;
         nb[t] = in ? x[((int64_t)zz * d.ny + yy) * d.nx + xx] : 0.0f;
     }
-    for (int c = 0; c < B; ++c) {
-        float acc = sb[c];
+    // 8 channels per 16-byte store (B % 8 == 0, ys % 8 == 0)
+    for (int c8 = 0; c8 < B; c8 += 8) {
+        u32x4 o;
 #pragma unroll
-        for (int t = 0; t < 27; ++t) acc = fmaf(sw[t * B + c], nb[t], acc);
-        y[v * ys + c] = f2bf(fmaxf(acc, 0.0f));
+        for (int k = 0; k < 4; ++k) {
+            const int c = c8 + 2 * k;
+            float a0 = sb[c], a1 = sb[c + 1];
+#pragma unroll
+            for (int t = 0; t < 27; ++t) {
+                a0 = fmaf(sw[t * B + c], nb[t], a0);
+                a1 = fmaf(sw[t * B + c + 1], nb[t], a1);
+            }
+            o[k] = (unsigned)f2bf(fmaxf(a0, 0.0f)) | ((unsigned)f2bf(fmaxf(a1, 0.0f)) << 16);
+        }
+        *reinterpret_cast<u32x4 *>(y + v * ys + c8) = o;
     }
 }
 
@@ -638,11 +658,17 @@ __global__ __launch_bounds__(256) void head_fwd(const u16 *__restrict__ a, int B
     const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (v >= V) return;
     float o0 = bh[0], o1 = bh[1], o2 = bh[2];
-    for (int c = 0; c < B; ++c) {
-        const float h = bf2f(a[v * B + c]);
-        o0 = fmaf(Wh[c], h, o0);
-        o1 = fmaf(Wh[B + c], h, o1);
-        o2 = fmaf(Wh[2 * B + c], h, o2);
+    // the voxel's B channels as 16-byte vectors (B % 8 == 0), in channel order
+    for (int c8 = 0; c8 < B; c8 += 8) {
+        const u32x4 q = *reinterpret_cast<const u32x4 *>(a + v * B + c8);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int c = c8 + k;
+            const float h = bf2f((u16)(q[k >> 1] >> (16 * (k & 1))));
+            o0 = fmaf(Wh[c], h, o0);
+            o1 = fmaf(Wh[B + c], h, o1);
+            o2 = fmaf(Wh[2 * B + c], h, o2);
+        }
     }
     out[3 * v] = o0;
     out[3 * v + 1] = o1;
@@ -655,47 +681,63 @@ __global__ __launch_bounds__(256) void head_fwd(const u16 *__restrict__ a, int B
 __global__ __launch_bounds__(256) void head_bwd(const u16 *__restrict__ a, int B, int64_t V,
                                                 const float *__restrict__ Wh, const float *__restrict__ dout,
                                                 u16 *__restrict__ dpre, float *__restrict__ part) {
-    __shared__ float red[6][256];
-    const int c = threadIdx.x % B, j = threadIdx.x / B, lanes = 256 / B;
+    // thread: channel octet c8 .. c8 + 7 (16-byte loads and stores) of every
+    // lanes-th voxel of the block's range; B % 8 == 0 and B / 8 divides 256
+    __shared__ float red[256 * 27];
+    const int groups = B / 8;
+    const int c8 = (threadIdx.x % groups) * 8, j = threadIdx.x / groups, lanes = 256 / groups;
     const int64_t per = (V + gridDim.x - 1) / gridDim.x;
     const int64_t v0 = (int64_t)blockIdx.x * per, v1 = min(V, v0 + per);
-    float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, b0 = 0.0f, b1 = 0.0f, b2 = 0.0f;
-    const float w0 = Wh[c], w1 = Wh[B + c], w2 = Wh[2 * B + c];
+    float gs[3][8], bs[3] = {0.0f, 0.0f, 0.0f}, w[3][8];
+#pragma unroll
+    for (int o = 0; o < 3; ++o)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            gs[o][k] = 0.0f;
+            w[o][k] = Wh[o * B + c8 + k];
+        }
     for (int64_t v = v0 + j; v < v1; v += lanes) {
         const float d0 = dout[3 * v], d1 = dout[3 * v + 1], d2 = dout[3 * v + 2];
-        const float h = bf2f(a[v * B + c]);
-        g0 = fmaf(d0, h, g0);
-        g1 = fmaf(d1, h, g1);
-        g2 = fmaf(d2, h, g2);
-        b0 += d0;
-        b1 += d1;
-        b2 += d2;
-        const float s = fmaf(d0, w0, fmaf(d1, w1, d2 * w2));
-        dpre[v * B + c] = f2bf(h > 0.0f ? s : 0.0f);
+        const u32x4 q = *reinterpret_cast<const u32x4 *>(a + v * B + c8);
+        u32x4 r;
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) {
+            unsigned packed = 0u;
+#pragma unroll
+            for (int h2 = 0; h2 < 2; ++h2) {
+                const int k = 2 * k2 + h2;
+                const float h = bf2f((u16)(q[k2] >> (16 * h2)));
+                gs[0][k] = fmaf(d0, h, gs[0][k]);
+                gs[1][k] = fmaf(d1, h, gs[1][k]);
+                gs[2][k] = fmaf(d2, h, gs[2][k]);
+                const float sv = fmaf(d0, w[0][k], fmaf(d1, w[1][k], d2 * w[2][k]));
+                packed |= (unsigned)f2bf(h > 0.0f ? sv : 0.0f) << (16 * h2);
+            }
+            r[k2] = packed;
+        }
+        *reinterpret_cast<u32x4 *>(dpre + v * B + c8) = r;
+        bs[0] += d0;
+        bs[1] += d1;
+        bs[2] += d2;
     }
-    red[0][threadIdx.x] = g0;
-    red[1][threadIdx.x] = g1;
-    red[2][threadIdx.x] = g2;
-    red[3][threadIdx.x] = b0;
-    red[4][threadIdx.x] = b1;
-    red[5][threadIdx.x] = b2;
+    float *mine = red + threadIdx.x * 27;
+#pragma unroll
+    for (int o = 0; o < 3; ++o) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) mine[o * 8 + k] = gs[o][k];
+        mine[24 + o] = bs[o];
+    }
     __syncthreads();
-    if (j == 0) {
-        float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
-        for (int q = 0; q < lanes; ++q) {
-            s0 += red[0][q * B + c];
-            s1 += red[1][q * B + c];
-            s2 += red[2][q * B + c];
+    float *out = part + (int64_t)blockIdx.x * (3 * B + 3);
+    for (int e = threadIdx.x; e < 3 * B + 3; e += 256) {
+        float t = 0.0f;
+        if (e < 3 * B) {  // weight (o, c)
+            const int o = e / B, c = e - o * B;
+            for (int qq = 0; qq < lanes; ++qq) t += red[(qq * groups + c / 8) * 27 + o * 8 + c % 8];
+        } else {  // bias o: the threads of octet 0 saw every voxel of the range
+            for (int qq = 0; qq < lanes; ++qq) t += red[(qq * groups) * 27 + 24 + (e - 3 * B)];
         }
-        float *o = part + (int64_t)blockIdx.x * (3 * B + 3);
-        o[c] = s0;
-        o[B + c] = s1;
-        o[2 * B + c] = s2;
-        if (c < 3) {  // every channel lane saw the same voxels: take channel 0's bias sums
-            float t = 0.0f;
-            for (int q = 0; q < lanes; ++q) t += red[3 + c][q * B];
-            o[3 * B + c] = t;
-        }
+        out[e] = t;
     }
 }
 
