@@ -70,12 +70,20 @@ struct Vol {
     int64_t V;
 };
 
+// Voxel v's coordinates.  32-bit division: the network's volumes have extents
+// of at most 1024, so v < 2^30.
 __device__ __forceinline__ void vox_coords(const Vol &d, int64_t v, int *x, int *y, int *z) {
-    const int64_t plane = (int64_t)d.nx * d.ny;
-    *z = (int)(v / plane);
-    const int64_t r = v - (int64_t)(*z) * plane;
-    *y = (int)(r / d.nx);
-    *x = (int)(r - (int64_t)(*y) * d.nx);
+    const unsigned plane = (unsigned)d.nx * (unsigned)d.ny, uv = (unsigned)v;
+    const unsigned zz = uv / plane, r = uv - zz * plane;
+    const unsigned yy = r / (unsigned)d.nx;
+    *z = (int)zz;
+    *y = (int)yy;
+    *x = (int)(r - yy * (unsigned)d.nx);
+}
+
+// i / n for an element index of a launch: 32-bit division where i fits.
+__device__ __forceinline__ int64_t idx_div(int64_t i, int n) {
+    return i < 0xffffffffLL ? (int64_t)((unsigned)i / (unsigned)n) : i / n;
 }
 
 // ---- implicit-GEMM 3x3x3 convolution on the matrix cores ---------------------
@@ -396,9 +404,15 @@ __global__ __launch_bounds__(256) void sum_chunks(const float *__restrict__ part
                                                   float *__restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
-    float s = 0.0f;
-    for (int c = 0; c < n_chunks; ++c) s += part[(int64_t)c * n + i];
-    out[i] = s;
+    // eight running sums (chunks c = u mod 8), so that eight loads are in
+    // flight, added in a fixed order at the end
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int c = 0;
+    for (; c + 8 <= n_chunks; c += 8)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s[u] += part[(int64_t)(c + u) * n + i];
+    for (int u = 0; c < n_chunks; ++c, ++u) s[u] += part[(int64_t)c * n + i];
+    out[i] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
 // Per-channel sums of a bf16 [V][s] slice (channels 0..C-1), C <= 256 and a
@@ -502,15 +516,34 @@ __global__ __launch_bounds__(256) void conv1_wgrad(const float *__restrict__ x, 
             }
             __syncthreads();
             if (cb + c < B) {
-                for (int v = j; v < kTX * kTY * kTZ; v += 8) {
-                    const int lx = v & 15, ly = (v >> 4) & 3, lz = v >> 6;
-                    const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
-                    if (gx >= d.nx || gy >= d.ny || gz >= d.nz) continue;
-                    const float gv = bf2f(dy[(((int64_t)gz * d.ny + gy) * d.nx + gx) * dys + cb + c]);
-                    const float *hb = xh + (lz * kHY + ly) * kHX + lx;
+                // runs of 4 voxels along x (64 per tile, 8 per thread): per
+                // (dz, dy) six halo values serve the run's 3 x 4 products
+                for (int run = j; run < kTX * kTY * kTZ / 4; run += 8) {
+                    const int lx = (run & 3) * 4, ly = (run >> 2) & 3, lz = run >> 4;
+                    const int gy = y0 + ly, gz = z0 + lz;
+                    float gv[4];
 #pragma unroll
-                    for (int t = 0; t < 27; ++t)
-                        acc[t] = fmaf(gv, hb[(t / 9) * (kHY * kHX) + ((t / 3) % 3) * kHX + t % 3], acc[t]);
+                    for (int i = 0; i < 4; ++i) {
+                        const int gx = x0 + lx + i;
+                        gv[i] = (gx < d.nx && gy < d.ny && gz < d.nz)
+                                    ? bf2f(dy[(((int64_t)gz * d.ny + gy) * d.nx + gx) * dys + cb + c])
+                                    : 0.0f;
+                    }
+#pragma unroll
+                    for (int pz = 0; pz < 3; ++pz)
+#pragma unroll
+                        for (int py = 0; py < 3; ++py) {
+                            const float *hb = xh + ((lz + pz) * kHY + ly + py) * kHX + lx;
+                            float h[6];
+#pragma unroll
+                            for (int q = 0; q < 6; ++q) h[q] = hb[q];
+#pragma unroll
+                            for (int px = 0; px < 3; ++px) {
+                                const int t = pz * 9 + py * 3 + px;
+#pragma unroll
+                                for (int i = 0; i < 4; ++i) acc[t] = fmaf(gv[i], h[i + px], acc[t]);
+                            }
+                        }
                 }
             }
         }
@@ -557,7 +590,7 @@ __global__ __launch_bounds__(256) void pool2_fwd(const u16 *__restrict__ a, int 
     const int groups = C / 8;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= dc.V * groups) return;
-    const int64_t p = i / groups;
+    const int64_t p = idx_div(i, groups);
     const int c8 = (int)(i - p * groups) * 8;
     int cx, cy, cz;
     vox_coords(dc, p, &cx, &cy, &cz);
@@ -582,7 +615,7 @@ __global__ __launch_bounds__(256) void up2_fwd(const u16 *__restrict__ src, Vol 
     const int groups = C / 8;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= dc.V * groups) return;
-    const int64_t p = i / groups;
+    const int64_t p = idx_div(i, groups);
     const int c8 = (int)(i - p * groups) * 8;
     int cx, cy, cz;
     vox_coords(dc, p, &cx, &cy, &cz);
@@ -597,7 +630,7 @@ __global__ __launch_bounds__(256) void up2_bwd_relu(const u16 *__restrict__ dcat
     const int groups = C / 8;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= dc.V * groups) return;
-    const int64_t p = i / groups;
+    const int64_t p = idx_div(i, groups);
     const int c8 = (int)(i - p * groups) * 8;
     int cx, cy, cz;
     vox_coords(dc, p, &cx, &cy, &cz);
@@ -631,7 +664,7 @@ __global__ __launch_bounds__(256) void skip_bwd_relu(const u16 *__restrict__ dsk
     const int groups = C / 8;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= d.V * groups) return;
-    const int64_t v = i / groups;
+    const int64_t v = idx_div(i, groups);
     const int c8 = (int)(i - v * groups) * 8;
     int px, py, pz;
     vox_coords(d, v, &px, &py, &pz);
