@@ -166,9 +166,11 @@ def recon_leg(max_iters: int):
 
 
 def fan_leg(max_iters: int, steps: int = 10):
-    """The fan-beam settings of the paper's Tabs. 2-3 (a stack of fan-beam
+    """The fan-beam settings of the paper's Tabs. 2-4 (a stack of fan-beam
     slices, one detector row per slice, 384 columns, 256^3 cube):
     * fwd+bwd+Adam iteration at 100,000 Gaussians and 60 views, ms;
+    * the same with the full objective, 150,000 isotropic Gaussians and the
+      fixed boxes 13^3 .. 19^3 of the box-size sweep (Tab. 4), ms;
     * 60-view sparse-view loop from 50,000 FBP-sampled Gaussians (3 voxels)
       with the full objective;
     * 90-degree limited-angle loop (90 views, 1 degree apart) from 50,000
@@ -195,6 +197,34 @@ def fan_leg(max_iters: int, steps: int = 10):
         "ms_per_iter": round(a.elapsed_time(b) / steps, 3),
         "stage_ms": {k: round(float(np.mean([x.elapsed_time(y) for x, y in v])), 3) for k, v in ev.items()}}}
     del it, prob
+    # The box-size sweep of the paper's Tab. 4 (60-view fan beam, full
+    # objective, fixed cuboid boxes 13^3 .. 19^3) with 150,000 isotropic
+    # Gaussians: fwd+bwd+Adam ms per iteration, each box from the same
+    # initial parameters.  The paper's times per iteration (its 1K-iteration
+    # runs on its GPU) also include densification, which is not in these.
+    prob = recon.cone_problem(n=150_000, geom=inputs.fan_workload(256, 60, 384), device="cuda")
+    prob.params["scale"][:, 1] = prob.params["scale"][:, 0]
+    prob.params["scale"][:, 2] = prob.params["scale"][:, 0]
+    init = {k: v.clone() for k, v in prob.params.items()}
+    sweep = []
+    for bh in (6, 7, 8, 9):
+        for k in init:
+            prob.params[k].copy_(init[k])
+        prob.k_sigma, prob.box_half = 0.0, bh
+        it = recon.Iteration(prob, objective="full")
+        for _ in range(3):
+            it.step()
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(steps):
+            it.step()
+        b.record()
+        torch.cuda.synchronize()
+        it.check()
+        sweep.append({"box": 2 * bh + 1, "ms_per_iter": round(a.elapsed_time(b) / steps, 3)})
+        del it
+    out["box_sweep_60view_full_objective_150k_isotropic"] = sweep
+    del prob, init
     loops = []
     for name, n_views, arc, init in (("sparse_view_60", 60, 2 * math.pi, "fbp"),
                                      ("limited_angle_90deg", 90, math.pi / 2, "random")):
