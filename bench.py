@@ -68,13 +68,13 @@ def count_samples(prob) -> int:
 
 REPO = os.path.dirname(os.path.abspath(__file__))
 COUNTER_FILE = os.path.join(REPO, "profiles", "counters_cone256.txt")
-KERNEL_SOURCE = {"backproject": "backproject_bricks<true>", "project_l1": "project_bundles<1,2>"}
+KERNEL_SOURCE = {"backproject": "backproject_bricks<true,false>", "project_l1": "project_bundles<1,2>"}
 # the source file each profiled kernel is built from (with internal.h)
 # kernels (and launches per stage) of the HBM-stage lines
 STAGE_KERNELS = {"voxelize": [("voxelize_tiles", 1)], "voxelize_backward": [("voxelize_grad", 1)],
                  "adam": [("adam_kernel", 4)], "projection_loss": [("ssim_fwd", 1), ("ssim_bwd", 1)],
                  "tv": [("tv_kernel", 1)]}
-KERNEL_FILE = {"backproject_bricks<true>": "project.hip", "project_bundles<1,2>": "project.hip",
+KERNEL_FILE = {"backproject_bricks<true,false>": "project.hip", "project_bundles<1,2>": "project.hip",
                "voxelize_tiles": "voxelize.hip", "voxelize_grad": "voxelize_bwd.hip",
                "ssim_fwd": "objective.hip", "ssim_bwd": "objective.hip", "tv_kernel": "objective.hip",
                "adam_kernel": "adam.hip"}

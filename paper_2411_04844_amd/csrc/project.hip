@@ -238,6 +238,11 @@ __device__ __forceinline__ void march_span(const float *vol, int sy, int sz, con
 // march_span over the LDS box: the tap's byte offset (cells within the box, so
 // every term is below 2^24) takes two 24-bit multiplies per sample instead of
 // two full-width multiplies and a scaling of each term.
+// PLANAR: the ray has no advance in z and a whole-voxel z position, so every
+// sample's z weight is 0 and the trilinear value is the bilinear one of the
+// lower plane, bit for bit (its last lerp adds 0 times a finite difference):
+// four taps instead of eight.
+template <bool PLANAR>
 __device__ __forceinline__ void march_box(const float *box, int sy, int sz, const int o[3], const Ray &r,
                                           int a, int e, float &acc) {
     const unsigned sy4 = 4u * (unsigned)sy, sz4 = 4u * (unsigned)sz;  // byte strides
@@ -248,13 +253,19 @@ __device__ __forceinline__ void march_box(const float *box, int sy, int sz, cons
         const int lx = (int)(ux >> 32), ly = (int)(uy >> 32), lz = (int)(uz >> 32);
         const float wx = (float)(unsigned)ux * kInv32;
         const float wy = (float)(unsigned)uy * kInv32;
-        const float wz = (float)(unsigned)uz * kInv32;
+        const float wz = PLANAR ? 0.0f : (float)(unsigned)uz * kInv32;
         const unsigned off = __umul24((unsigned)lz, sz4) + __umul24((unsigned)ly, sy4) + ((unsigned)lx << 2);
-        acc += trilinear(reinterpret_cast<const float *>(reinterpret_cast<const char *>(box) + off), sy, sz, wx,
-                         wy, wz);
+        const float *q = reinterpret_cast<const float *>(reinterpret_cast<const char *>(box) + off);
+        if (PLANAR) {
+            const float c00 = fmaf(wx, q[1] - q[0], q[0]);
+            const float c10 = fmaf(wx, q[sy + 1] - q[sy], q[sy]);
+            acc += fmaf(wy, c10 - c00, c00);
+        } else {
+            acc += trilinear(q, sy, sz, wx, wy, wz);
+        }
         ux += r.DU[0];
         uy += r.DU[1];
-        uz += r.DU[2];
+        if (!PLANAR) uz += r.DU[2];
     }
 }
 
@@ -407,6 +418,10 @@ __global__ __launch_bounds__(256) void project_bundles(const float *__restrict__
             kr[3] = max(kr[3], k1[q]);
         }
     }
+    // one ray per thread (fan and parallel beams): the wave marches the
+    // lower plane only where all of its rays are planar (see march_box)
+    bool planar = false;
+    if constexpr (NR == 1) planar = __ballot(!ok[0] || (r[0].DU[2] == 0 && (unsigned)r[0].U[2] == 0u)) == __ballot(1);
     block_bounds(kr, red[1], wave, lane);
     const int kmin = kr[0], kmax = kr[3];
     const int sy = (int)p.px, sz = (int)p.plane;
@@ -452,7 +467,12 @@ __global__ __launch_bounds__(256) void project_bundles(const float *__restrict__
             __syncthreads();
 #pragma unroll
             for (int q = 0; q < NR; ++q)
-                if (has[q]) march_box(box, nx, nx * ny, o, r[q], a[q], e[q], acc[q]);
+                if (has[q]) {
+                    if (NR == 1 && planar)
+                        march_box<true>(box, nx, nx * ny, o, r[q], a[q], e[q], acc[q]);
+                    else
+                        march_box<false>(box, nx, nx * ny, o, r[q], a[q], e[q], acc[q]);
+                }
             __syncthreads();
         } else {
             const int o0[3] = {0, 0, 0};
@@ -594,7 +614,7 @@ __device__ __forceinline__ double fixed_scale(const unsigned *maxbits, float sca
 struct BpScale {
     double s;         // fixed-point scale: gr = proj * length_scale * step * s
     double inv_s;     // 1 / s
-    int packed;       // 1: packed tile (backproject_bricks<true>), 0: 64-bit tile
+    int packed;       // 1: packed tile (backproject_bricks<true, .>), 0: 64-bit tile
     int drain_above;  // packed: a word is moved when a half exceeds this in magnitude
 };
 constexpr double kHalfCap = 2147483648.0 - 134217728.0;  // 2^31 - 2^27: the margin covers the
@@ -918,6 +938,14 @@ __device__ __forceinline__ void flush_packed(unsigned long long *tile, unsigned 
     atomicAdd(q + kPXY + kPX, pack_pair(e[6], e[7]));
 }
 
+// Adds the four lower-plane corner values of in-brick cell `word` (planar
+// rays, whose upper-plane values are zero) as two pairs along x.
+__device__ __forceinline__ void flush_planar(unsigned long long *tile, unsigned word, const float (&e)[4]) {
+    unsigned long long *q = tile + word;
+    atomicAdd(q, pack_pair(e[0], e[1]));
+    atomicAdd(q + kPX, pack_pair(e[2], e[3]));
+}
+
 // Tile entry (packed: word) of the lower corner of in-brick cell (x, y, z):
 // 24-bit products.
 template <bool PACKED>
@@ -932,7 +960,14 @@ __device__ __forceinline__ unsigned cell_index(long long ux, long long uy, long 
 // their eight corner weights in registers and adds them to the tile once per
 // cell visit.  The fixed-point scale leaves room for the largest number of
 // samples one cell can hold.
-template <bool PACKED>
+// PLANE_OK: the launch may hold planar rays (fan beams whose rows lie on voxel
+// centre planes: no advance in z and a whole-voxel z position).  Their
+// samples' z weights are exactly 0, so the upper-plane corner values stay at
+// the accumulators' start of +-1/2 and add the integer 0: where every active
+// lane of a wave holds a planar ray, the wave marches the lower plane only
+// (four corner values, two packed adds per cell visit), with a tile equal to
+// the general march's bit for bit.
+template <bool PACKED, bool PLANE_OK>
 __device__ __forceinline__ void march_segments(unsigned long long *tile, const RayRec *rays,
                                                const unsigned short *segs, int nsegs, int seg_shift) {
     const int t = threadIdx.x;
@@ -979,6 +1014,31 @@ __device__ __forceinline__ void march_segments(unsigned long long *tile, const R
         const unsigned hi = gr < 0.0f ? 0xffffffffu : 0u;
         const float a_init = PACKED ? (gr < 0.0f ? -0.5f : 0.5f) : (gr < 0.0f ? -1.0f : 1.0f);
         unsigned cell = cell_index<PACKED>(ux, uy, uz);
+        if (PACKED && PLANE_OK && __ballot(dz == 0 && (unsigned)uz == 0u) == __ballot(1)) {
+            // the same products as below with fz = 0: z0 = gr, z1 = 0
+            float acc4[4] = {a_init, a_init, a_init, a_init};
+            for (int i = 0; i < cnt; ++i) {
+                const unsigned here = cell_index<PACKED>(ux, uy, uz);
+                const float fx = (float)(unsigned)ux, fy = (float)(unsigned)uy;
+                ux += dx;
+                uy += dy;
+                if (here != cell) {
+                    flush_planar(tile, cell, acc4);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc4[c] = a_init;
+                    cell = here;
+                }
+                const float wy = fy * kInv32;
+                const float y01 = gr * wy, y00 = fmaf(-gr, wy, gr);
+                const float wx = fx * kInv32, ox = fmaf(-fx, kInv32, 1.0f);
+                acc4[0] = fmaf(y00, ox, acc4[0]);
+                acc4[1] = fmaf(y00, wx, acc4[1]);
+                acc4[2] = fmaf(y01, ox, acc4[2]);
+                acc4[3] = fmaf(y01, wx, acc4[3]);
+            }
+            flush_planar(tile, cell, acc4);
+            continue;
+        }
         float acc[8] = {a_init, a_init, a_init, a_init, a_init, a_init, a_init, a_init};
         for (int i = 0; i < cnt; ++i) {
             const unsigned here = cell_index<PACKED>(ux, uy, uz);
@@ -1032,7 +1092,9 @@ __device__ __forceinline__ void march_segments(unsigned long long *tile, const R
 // and written to) the brick's staging sums at the end; the packed tile's
 // words are added into them when a half nears the end of its range (checked
 // after every view) and at the end.
-template <bool PACKED>
+// PLANE_OK: the planar march where a wave's rays allow it (launched for fan
+// beams; the other instances compile it out).
+template <bool PACKED, bool PLANE_OK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DGR_BP_WAVES, DGR_BP_WAVES))) void backproject_bricks(
     const RayTab *__restrict__ tab, int j0, int nj, GeomDev G, Bricks bk, const ushort4 *__restrict__ rect,
     int seg_shift, int accumulate, const BpScale *__restrict__ sc, long long *__restrict__ staging) {
@@ -1219,7 +1281,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DGR_BP_WAVE
         // (unconditional load, row 0 for lanes without a candidate: no
         // branch, so nothing waits for the load before the march)
         const RayTab rt_next = tab[have ? row_of(j, rc, inu, cb + t) : 0];
-        march_segments<PACKED>(tile, rays, segs, ns, seg_shift);
+        march_segments<PACKED, PLANE_OK>(tile, rays, segs, ns, seg_shift);
         n = have ? finish(rt_next, rec) : 0;
         __syncthreads();
         if (t == 0) {
@@ -1481,11 +1543,16 @@ extern "C" dgr_status dgr_backproject(const float *proj, const dgr_grid *grid,
         ray_table<<<dim3((unsigned)((nrays + 255) / 256)), dim3(256), 0, st>>>(proj, G, g, j0, nrays, w.scale,
                                                                               w.tab);
         DGR_LAUNCH_CHECK();
-        // the instance whose tile format the scale kernel did not choose returns at once
-        backproject_bricks<true><<<dim3((unsigned)bk.count()), dim3(256), 0, st>>>(
-            w.tab, j0, nj, G, bk, w.rect, seg_shift, j0 > 0 ? 1 : 0, w.scale, w.staging);
+        // the instance whose tile format the scale kernel did not choose returns
+        // at once; fan beams take the packed instance with the planar march
+        if (geom->kind == DGR_FAN)
+            backproject_bricks<true, true><<<dim3((unsigned)bk.count()), dim3(256), 0, st>>>(
+                w.tab, j0, nj, G, bk, w.rect, seg_shift, j0 > 0 ? 1 : 0, w.scale, w.staging);
+        else
+            backproject_bricks<true, false><<<dim3((unsigned)bk.count()), dim3(256), 0, st>>>(
+                w.tab, j0, nj, G, bk, w.rect, seg_shift, j0 > 0 ? 1 : 0, w.scale, w.staging);
         DGR_LAUNCH_CHECK();
-        backproject_bricks<false><<<dim3((unsigned)bk.count()), dim3(256), 0, st>>>(
+        backproject_bricks<false, false><<<dim3((unsigned)bk.count()), dim3(256), 0, st>>>(
             w.tab, j0, nj, G, bk, w.rect, seg_shift, j0 > 0 ? 1 : 0, w.scale, w.staging);
         DGR_LAUNCH_CHECK();
     }
