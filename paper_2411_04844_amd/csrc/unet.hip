@@ -160,8 +160,8 @@ __global__ __launch_bounds__(256) void conv3_tile(const u16 *__restrict__ x, int
 #pragma unroll
         for (int n = 0; n < NT; ++n) acc[m][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     // 16-byte halo loads per thread (the last partial), issued kBatch at a time
-    // before their LDS stores (all of them where the registers allow: with
-    // 64 output channels the accumulators leave room for half)
+    // before their LDS stores: all at once, or in two batches for the
+    // 64-channel instance, which holds 64 accumulator registers besides
     constexpr int kLoads = (kHalo * 4 + 255) / 256;
     constexpr int kBatch = NT >= 4 ? (kLoads + 1) / 2 : kLoads;
     for (int kb = 0; kb < cin; kb += 32) {
