@@ -960,10 +960,15 @@ dgr_status check_unet(const int32_t dims[3], int B, Net *n, void *ws, size_t ws_
 dgr_status launch_conv(const u16 *x, int xs, const Vol &d, int cin, const u16 *w, const float *bias,
                        int cout, int relu, u16 *y, int ys, hipStream_t st, bool frag = true) {
     const int64_t tiles = (int64_t)((d.nx + kTX - 1) / kTX) * ((d.ny + kTY - 1) / kTY) * ((d.nz + kTZ - 1) / kTZ);
-    // output channels per work-group: 64 where they divide, else 32
-    const int per = cout % 64 == 0 ? 64 : 32;
+    // output channels per work-group: 64 where they divide, else 32; 16 where
+    // that leaves fewer than two work-groups per CU (the deep levels: 16^3
+    // voxels are 16 tiles), trading fragment reuse for parallelism
+    int per = cout % 64 == 0 ? 64 : 32;
+    if (frag && tiles * (cout / per) < 512) per = 16;
     const dim3 grid((unsigned)tiles, (unsigned)(cout / per));
-    if (per == 64 && frag)
+    if (per == 16)
+        conv3_tile<1, true><<<grid, dim3(256), 0, st>>>(x, xs, d, cin, w, bias, cout, relu, y, ys);
+    else if (per == 64 && frag)
         conv3_tile<4, true><<<grid, dim3(256), 0, st>>>(x, xs, d, cin, w, bias, cout, relu, y, ys);
     else if (frag)
         conv3_tile<2, true><<<grid, dim3(256), 0, st>>>(x, xs, d, cin, w, bias, cout, relu, y, ys);
