@@ -94,14 +94,15 @@ __global__ __launch_bounds__(256) void voxelize_grad(GaussRec *__restrict__ rec,
     m1x = wave_sum(m1x); m1y = wave_sum(m1y); m1z = wave_sum(m1z);
     Mxx = wave_sum(Mxx); Myy = wave_sum(Myy); Mzz = wave_sum(Mzz);
     Mxy = wave_sum(Mxy); Mxz = wave_sum(Mxz); Myz = wave_sum(Myz);
-    // The ten moments replace the Gaussian's record (its wave has read it);
-    // chain_rule turns them into gradients with one lane per Gaussian.
+    // The ten moments replace the Gaussian's record, in its own 64-byte slot
+    // (its wave has read it; no other wave reads that slot); chain_rule turns
+    // them into gradients with one lane per Gaussian.
     if (lane == 0) {
         GaussMoments mo;
         mo.m[0] = M0; mo.m[1] = m1x; mo.m[2] = m1y; mo.m[3] = m1z;
         mo.m[4] = Mxx; mo.m[5] = Myy; mo.m[6] = Mzz; mo.m[7] = Mxy; mo.m[8] = Mxz; mo.m[9] = Myz;
         mo.rho = r.rho;
-        reinterpret_cast<GaussMoments *>(rec)[gi] = mo;
+        *reinterpret_cast<GaussMoments *>(rec + gi) = mo;
     }
 }
 
@@ -113,7 +114,7 @@ __global__ __launch_bounds__(256) void chain_rule(const GaussRec *__restrict__ r
                                                   float *__restrict__ dquat, float *__restrict__ ddensity) {
     const int64_t gi = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (gi >= n) return;
-    const GaussMoments mo = reinterpret_cast<const GaussMoments *>(rec)[gi];
+    const GaussMoments mo = *reinterpret_cast<const GaussMoments *>(rec + gi);
     const float M0 = mo.m[0], m1x = mo.m[1], m1y = mo.m[2], m1z = mo.m[3];
     const float Mxx = mo.m[4], Myy = mo.m[5], Mzz = mo.m[6], Mxy = mo.m[7], Mxz = mo.m[8], Myz = mo.m[9];
     const double ih[3] = {g.inv_h[0], g.inv_h[1], g.inv_h[2]};
