@@ -307,6 +307,8 @@ __device__ __forceinline__ u32x4 load8(const u16 *p, const Vol &d, int gx, int g
 // tiles of X and dY, which then stay in that XCD's L2.
 constexpr int kXcds = 8;
 
+// Two waves per SIMD (the LDS holds two work-groups per CU): the registers
+// that carry the next tile's loads fit in the 256 that leaves each wave.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void conv3_wgrad(const u16 *__restrict__ x, int xs, Vol d, int cin,
                                                    const u16 *__restrict__ dy, int dys, int cout, int nc,
                                                    float *__restrict__ part) {
